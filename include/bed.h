@@ -1,0 +1,163 @@
+/*
+ * bed.h -- C ABI of the MI355X batched symmetric eigensolver.
+ *
+ * Method: Householder tridiagonalization followed by the batch-efficient
+ * divide-and-conquer of Y. Song, "A Short Note on Batch-efficient Divide-and-
+ * Conquer Algorithm for EigenDecomposition" (arXiv 2604.27325): rank-one
+ * tearing (Sec. 2.1, Eq. (1)-(3)), 2x2 Givens leaves (Sec. 2.2), secular
+ * equation under bounded interlacing (Sec. 2.3.1, Eq. (8)-(12)), hybrid-section
+ * (Sec. 2.3.2, Eq. (13)-(17)), Halley (Sec. 2.3.3, Eq. (20)-(21)), progressive
+ * removal of converged work (Sec. 2.3.4, Eq. (22)) and Loewner/Gu-Eisenstat
+ * eigenvectors (Sec. 2.3.5, Eq. (23)-(25)).  The problem statement is the
+ * note's: a mini-batch of symmetric matrices (Sec. 1, Sec. 2.1 "B x C x C")
+ * mapped to the eigenvalue tensor lambda in R^{B x C} (Sec. 2.3.1, Eq. (12))
+ * and, when required, the eigenvector matrices (Sec. 2.3.5).
+ *
+ * Conventions shared by every entry point
+ *   Layout     packed batch-major.  Matrix b is row-major n_b x n_b starting at
+ *              element sum_{c<b} n_c^2 of A (and of Q, dA); its eigenvalues
+ *              start at element sum_{c<b} n_c of lambda.  A uniform batch is
+ *              exactly a contiguous (batch, n, n) / (batch, n) array.
+ *   Input      only the lower triangle of each A_b is read (uplo = 'L').
+ *   Output     lambda ascending; Q[b][i][j] = component i of eigenvector j;
+ *              each column sign-canonical (largest-magnitude entry positive,
+ *              lowest index on exact ties).
+ *   Sizes      1 <= n_b <= 64.  n_b > 64 is reserved (BED_ERR_UNSUPPORTED).
+ *   Memory     A, lambda, Q, info, dlambda, dQ, dA are DEVICE pointers owned
+ *              by the caller.  n arrays are HOST pointers, read during the
+ *              call only.  FP32 data needs 4-byte, FP64 8-byte alignment.
+ *   Aliasing   A is read-only, except that Q == A (in place) is allowed; any
+ *              other overlap between inputs and outputs is undefined.
+ *   Streams    `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *              enqueue work and return without synchronizing.
+ *   Errors     synchronous: a bed_status; the message of the last failure of
+ *              the calling thread is in bed_last_error().  Asynchronous, per
+ *              matrix, in info[b] (info may be NULL):
+ *                0   success;
+ *               -1   non-finite entry in the lower triangle (lambda, Q = NaN);
+ *                k>0 k secular roots stopped at the iteration cap (results
+ *                    returned, accuracy not guaranteed).
+ *   Threads    calls on distinct plans/streams are thread-safe; a server is
+ *              internally synchronized.
+ */
+#ifndef BED_H
+#define BED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { BED_F32 = 0, BED_F64 = 1 } bed_dtype;
+
+typedef enum {
+    BED_OK = 0,
+    BED_ERR_INVALID_ARG = 1, /* bad size, null or misaligned pointer, bad dtype   */
+    BED_ERR_UNSUPPORTED = 2, /* n > 64                                            */
+    BED_ERR_HIP = 3,         /* a HIP runtime call failed (see bed_last_error)    */
+    BED_ERR_NOMEM = 4,       /* device or host allocation failed / over budget    */
+    BED_ERR_CAPTURE = 5,     /* call would allocate or copy during stream capture */
+    BED_ERR_BUSY = 6         /* server: admission refused (slots or memory full)  */
+} bed_status;
+
+/* Launch schedule of a plan.  Zero fields mean "autotuned / default".
+ *   threads_big   threads per matrix for the n > 32 size class (64..512)
+ *   threads_mid   threads per matrix for 16 < n <= 32 (64 or 128)
+ *   waves_per_cu  resident teams per compute unit for the persistent launch
+ *   order         0: largest n first (LPT), 1: input order
+ *   persistent    1: one persistent launch pulls matrices from a device work
+ *                 counter (progressive removal at batch level); 0: one
+ *                 workgroup per matrix                                          */
+typedef struct bed_tune {
+    int32_t threads_big;
+    int32_t threads_mid;
+    int32_t waves_per_cu;
+    int32_t order;
+    int32_t persistent;
+} bed_tune;
+
+typedef struct bed_plan bed_plan;
+
+/* One-shot solve: lambda, Q (and info) for a packed batch.  batch == 0 is a
+ * no-op.  Uses an internal plan cache keyed by (dtype, n[]); the first call
+ * for a new mixed-size n[] allocates its descriptor (refused under capture). */
+bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
+                     void *Q, int32_t *info, void *stream);
+
+/* Eigenvalues only (the note computes eigenvectors "when required",
+ * Sec. 2.3.5): Q is not produced; same kernel path, no Q store. */
+bed_status bed_syevals(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
+                       void *lambda, int32_t *info, void *stream);
+
+/* Plans: descriptors (offsets, size classes, work order) and the schedule
+ * are built once; bed_plan_run enqueues one launch per size class (or one
+ * persistent launch) and allocates nothing, so it may be captured into a HIP
+ * graph.  tune == NULL takes the autotuner's choice for this size mix.
+ * bed_plan_create during stream capture of the current thread's stream
+ * returns BED_ERR_CAPTURE. */
+bed_status bed_plan_create(bed_plan **plan, bed_dtype dt, int64_t batch, const int32_t *n,
+                           const bed_tune *tune);
+bed_status bed_plan_run(const bed_plan *plan, const void *A, void *lambda, void *Q,
+                        int32_t *info, void *stream);
+bed_status bed_plan_get_tune(const bed_plan *plan, bed_tune *out);
+void bed_plan_destroy(bed_plan *plan);
+
+/* Autotuner: times the candidate schedules for this size mix on `stream`
+ * (synchronizing it) and stores the winner in the process cache (and in the
+ * JSON file named by BED_TUNE_CACHE when set).  A, lambda, Q are scratch
+ * buffers of the packed sizes.  The chosen schedule is written to *out. */
+bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
+                        void *Q, void *stream, bed_tune *out);
+
+/* Backward of A = Q diag(lambda) Q^T (for differentiable use, Sec. 1):
+ *   dA = Q ( diag(dlambda) + sym(F o (Q^T dQ)) ) Q^T,  sym(X) = (X + X^T)/2,
+ *   F_ij = 1/(lambda_j - lambda_i) for i != j, F_ij = 0 when
+ *   |lambda_i - lambda_j| <= degeneracy_eps * max(1, max_i |lambda_i|).
+ * dlambda or dQ may be NULL (treated as zero).  dA has A's layout and is
+ * symmetric.  degeneracy_eps <= 0 selects 1e3 * unit roundoff of dt. */
+bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int32_t *n, const void *lambda,
+                              const void *Q, const void *dlambda, const void *dQ, void *dA,
+                              double degeneracy_eps, void *stream);
+
+/* Serving: continuous batching of eigendecomposition requests.
+ *   streams      device streams the server launches on (1..16)
+ *   max_inflight matrices admitted but not yet completed (0 = unlimited)
+ *   mem_budget   bytes of request buffers admitted at once (0 = unlimited)
+ *   max_step     most matrices packed into one launch (0 = 4096)
+ * A request's A/lambda/Q are caller-owned device buffers that must stay alive
+ * until bed_server_poll reports it done.  Each request is solved by the same
+ * per-matrix kernel configuration (a function of n and dtype only), so its
+ * result is bitwise identical alone and in any mix. */
+typedef struct bed_server_opts {
+    int32_t streams;
+    int32_t max_inflight;
+    int64_t mem_budget;
+    int32_t max_step;
+    int32_t device;
+} bed_server_opts;
+
+typedef struct bed_server bed_server;
+
+bed_status bed_server_create(bed_server **s, const bed_server_opts *o);
+/* Admits one request of `count` matrices of size n (packed as above).  Returns
+ * BED_ERR_BUSY when admission is refused by the slot or memory limit (nothing
+ * is queued; retry later).  *ticket identifies the request. */
+bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t count, int32_t n, const void *A,
+                             void *lambda, void *Q, int32_t *info, uint64_t *ticket);
+/* *done = 1 once the request's results are complete in device memory;
+ * *latency_us (may be NULL) = submit-to-completion-observed time. */
+bed_status bed_server_poll(bed_server *s, uint64_t ticket, int32_t *done, double *latency_us);
+/* Blocks until every admitted request has completed. */
+bed_status bed_server_drain(bed_server *s);
+void bed_server_destroy(bed_server *s);
+
+const char *bed_status_string(bed_status st);
+const char *bed_last_error(void);
+/* Library version, as major*10000 + minor*100 + patch. */
+int32_t bed_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

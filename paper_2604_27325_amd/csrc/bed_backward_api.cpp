@@ -1,0 +1,77 @@
+// bed_backward_api.cpp -- C ABI of the backward kernel.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "bed_host.hpp"
+
+using namespace bed;
+
+namespace {
+struct BwdPlan {
+    WorkItem *d_items = nullptr;
+    int count = 0;
+    int nmax = 64;
+};
+std::mutex g_bwd_mu;
+std::map<std::pair<int, std::vector<int32_t>>, BwdPlan> g_bwd_cache;
+}  // namespace
+
+extern "C" bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int32_t *n,
+                                         const void *lambda, const void *Q, const void *dlambda,
+                                         const void *dQ, void *dA, double degeneracy_eps,
+                                         void *stream)
+{
+    bed_status st = check_sizes(dt, batch, n);
+    if (st != BED_OK) return st;
+    if (batch == 0) return BED_OK;
+    if ((st = check_ptr(lambda, dt, "lambda", false)) != BED_OK) return st;
+    if ((st = check_ptr(Q, dt, "Q", false)) != BED_OK) return st;
+    if ((st = check_ptr(dlambda, dt, "dlambda", true)) != BED_OK) return st;
+    if ((st = check_ptr(dQ, dt, "dQ", true)) != BED_OK) return st;
+    if ((st = check_ptr(dA, dt, "dA", false)) != BED_OK) return st;
+    const double eps = degeneracy_eps > 0 ? degeneracy_eps
+                                          : 1e3 * (dt == BED_F32 ? 0x1p-24 : 0x1p-53);
+    hipStream_t s = (hipStream_t)stream;
+    const bool uniform = std::all_of(n, n + batch, [&](int32_t v) { return v == n[0]; });
+    if (uniform) {
+        hipError_t e = launch_backward_uniform(dt, n[0], lambda, Q, dlambda, dQ, dA, n[0], batch,
+                                               eps, s);
+        return e == hipSuccess ? BED_OK : hip_fail(e, "backward launch");
+    }
+    BwdPlan p;
+    {
+        std::lock_guard<std::mutex> lk(g_bwd_mu);
+        auto key = std::make_pair((int)dt, std::vector<int32_t>(n, n + batch));
+        auto it = g_bwd_cache.find(key);
+        if (it != g_bwd_cache.end()) {
+            p = it->second;
+        } else {
+            if (stream_capturing(s))
+                return fail(BED_ERR_CAPTURE, "first backward for a new size mix during capture");
+            std::vector<WorkItem> items;
+            int64_t offA = 0, offL = 0;
+            for (int64_t b = 0; b < batch; ++b) {
+                items.push_back(WorkItem{offA, offL, n[b], (int32_t)b});
+                offA += (int64_t)n[b] * n[b];
+                offL += n[b];
+                p.nmax = std::max(p.nmax, (int)n[b]);
+            }
+            p.nmax = *std::max_element(n, n + batch);
+            p.count = (int)batch;
+            hipError_t e = hipMalloc(&p.d_items, sizeof(WorkItem) * items.size());
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
+            e = hipMemcpy(p.d_items, items.data(), sizeof(WorkItem) * items.size(),
+                          hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(p.d_items);
+                return hip_fail(e, "hipMemcpy(work list)");
+            }
+            g_bwd_cache.emplace(std::move(key), p);
+        }
+    }
+    hipError_t e = launch_backward(dt, p.nmax, lambda, Q, dlambda, dQ, dA, p.d_items, p.count,
+                                   eps, s);
+    return e == hipSuccess ? BED_OK : hip_fail(e, "backward launch");
+}

@@ -1,0 +1,65 @@
+// bed_internal.hpp -- interface between the C-ABI host code and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/bed.h"
+
+namespace bed {
+
+// One matrix of a work list: packed offsets, size, position in the batch.
+struct WorkItem {
+    int64_t offA;  // element offset of A_b (and Q_b)
+    int64_t offL;  // element offset of lambda_b
+    int32_t n;
+    int32_t idx;   // batch index (for info)
+};
+
+// One matrix of a serving step: absolute device pointers (requests own
+// separate buffers).
+struct PtrItem {
+    const void *A;
+    void *lam;
+    void *Q;
+    int32_t *info;
+    int32_t n;
+    int32_t pad;
+};
+
+// Size classes: a team of `nt` threads solves matrices with n <= nmax.
+struct TeamShape {
+    int nmax;
+    int nt;
+};
+
+bool team_supported(bed_dtype dt, TeamShape ts);
+
+// One workgroup per matrix of a uniform batch.
+hipError_t launch_uniform(bed_dtype dt, TeamShape ts, const void *A, int n, int64_t batch,
+                          void *lam, void *Q, int32_t *info, hipStream_t s);
+
+// Work-list launch.  counter == nullptr: workgroup i handles items i, i+grid,
+// ... (static).  counter != nullptr: persistent workgroups pull items from
+// counter[0]; counter[1] counts finished workgroups and the last one resets
+// both to zero, so the launch can be replayed (e.g. from a HIP graph).
+hipError_t launch_list(bed_dtype dt, TeamShape ts, const void *A, void *lam, void *Q,
+                       int32_t *info, const WorkItem *items, int count, int *counter, int grid,
+                       hipStream_t s);
+
+// One workgroup per pointer item (serving steps).
+hipError_t launch_ptrlist(bed_dtype dt, TeamShape ts, const PtrItem *items, int count,
+                          hipStream_t s);
+
+// Resident workgroups per CU for a team shape (occupancy query).
+int blocks_per_cu(bed_dtype dt, TeamShape ts);
+
+// Backward kernel over a work list (one workgroup per matrix).
+hipError_t launch_backward(bed_dtype dt, int nmax, const void *lam, const void *Q,
+                           const void *dlam, const void *dQ, void *dA, const WorkItem *items,
+                           int count, double eps, hipStream_t s);
+hipError_t launch_backward_uniform(bed_dtype dt, int nmax, const void *lam, const void *Q,
+                                   const void *dlam, const void *dQ, void *dA, int n,
+                                   int64_t batch, double eps, hipStream_t s);
+
+}  // namespace bed

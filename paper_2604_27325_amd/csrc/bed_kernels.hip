@@ -1,0 +1,169 @@
+// bed_kernels.hip -- kernel entry points and their instantiations for gfx950.
+#include "bed_internal.hpp"
+#include "bed_syevd.hpp"
+
+namespace bed {
+
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ lam,
+                T *__restrict__ Q, int32_t *__restrict__ info)
+{
+    __shared__ Smem<T, NMAX, NT> S;
+    const int64_t b = blockIdx.x;
+    if (b >= batch) return;
+    const int64_t n2 = (int64_t)n * n;
+    syevd_team<T, NMAX, NT>(A + b * n2, n, lam + b * n, Q ? Q + b * n2 : nullptr,
+                            info ? info + b : nullptr, S, threadIdx.x);
+}
+
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+k_syevd_list(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
+             int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count,
+             int *counter)
+{
+    __shared__ Smem<T, NMAX, NT> S;
+    __shared__ int cur;
+    if (counter == nullptr) {
+        for (int it = blockIdx.x; it < count; it += gridDim.x) {
+            const WorkItem w = items[it];
+            syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
+                                    info ? info + w.idx : nullptr, S, threadIdx.x);
+        }
+        return;
+    }
+    // Persistent schedule: converged workgroups immediately take the next
+    // matrix, so the batch shrinks as work completes (Sec. 2.3.4, Eq. (22)).
+    for (;;) {
+        if (threadIdx.x == 0) cur = atomicAdd(&counter[0], 1);
+        __syncthreads();
+        const int it = cur;
+        __syncthreads();
+        if (it >= count) break;
+        const WorkItem w = items[it];
+        syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
+                                info ? info + w.idx : nullptr, S, threadIdx.x);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counter[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&counter[0], 0);
+            atomicExch(&counter[1], 0);
+        }
+    }
+}
+
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+k_syevd_ptrlist(const PtrItem *__restrict__ items, int count)
+{
+    __shared__ Smem<T, NMAX, NT> S;
+    if ((int)blockIdx.x >= count) return;
+    const PtrItem w = items[blockIdx.x];
+    syevd_team<T, NMAX, NT>((const T *)w.A, w.n, (T *)w.lam, (T *)w.Q, w.info, S, threadIdx.x);
+}
+
+// ---------------------------------------------------------------- dispatch
+#define BED_SHAPES(X) X(16, 64) X(32, 64) X(32, 128) X(64, 64) X(64, 128) X(64, 256) X(64, 512)
+
+bool team_supported(bed_dtype dt, TeamShape ts)
+{
+    (void)dt;
+#define X(NM, NTT) if (ts.nmax == NM && ts.nt == NTT) return true;
+    BED_SHAPES(X)
+#undef X
+    return false;
+}
+
+template <typename T>
+static hipError_t uniform_t(TeamShape ts, const void *A, int n, int64_t batch, void *lam, void *Q,
+                            int32_t *info, hipStream_t s)
+{
+#define X(NM, NTT)                                                                          \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                    \
+        hipLaunchKernelGGL((k_syevd_uniform<T, NM, NTT>), dim3((unsigned)batch), dim3(NTT), \
+                           0, s, (const T *)A, n, batch, (T *)lam, (T *)Q, info);           \
+        return hipGetLastError();                                                           \
+    }
+    BED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_uniform(bed_dtype dt, TeamShape ts, const void *A, int n, int64_t batch,
+                          void *lam, void *Q, int32_t *info, hipStream_t s)
+{
+    if (batch <= 0) return hipSuccess;
+    return dt == BED_F32 ? uniform_t<float>(ts, A, n, batch, lam, Q, info, s)
+                         : uniform_t<double>(ts, A, n, batch, lam, Q, info, s);
+}
+
+template <typename T>
+static hipError_t list_t(TeamShape ts, const void *A, void *lam, void *Q, int32_t *info,
+                         const WorkItem *items, int count, int *counter, int grid, hipStream_t s)
+{
+#define X(NM, NTT)                                                                            \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                      \
+        hipLaunchKernelGGL((k_syevd_list<T, NM, NTT>), dim3((unsigned)grid), dim3(NTT), 0, s, \
+                           (const T *)A, (T *)lam, (T *)Q, info, items, count, counter);      \
+        return hipGetLastError();                                                             \
+    }
+    BED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_list(bed_dtype dt, TeamShape ts, const void *A, void *lam, void *Q,
+                       int32_t *info, const WorkItem *items, int count, int *counter, int grid,
+                       hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    return dt == BED_F32 ? list_t<float>(ts, A, lam, Q, info, items, count, counter, grid, s)
+                         : list_t<double>(ts, A, lam, Q, info, items, count, counter, grid, s);
+}
+
+template <typename T>
+static hipError_t ptrlist_t(TeamShape ts, const PtrItem *items, int count, hipStream_t s)
+{
+#define X(NM, NTT)                                                                            \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                      \
+        hipLaunchKernelGGL((k_syevd_ptrlist<T, NM, NTT>), dim3((unsigned)count), dim3(NTT), 0, \
+                           s, items, count);                                                  \
+        return hipGetLastError();                                                             \
+    }
+    BED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_ptrlist(bed_dtype dt, TeamShape ts, const PtrItem *items, int count,
+                          hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    return dt == BED_F32 ? ptrlist_t<float>(ts, items, count, s)
+                         : ptrlist_t<double>(ts, items, count, s);
+}
+
+template <typename T>
+static int bpc_t(TeamShape ts)
+{
+    int nb = 0;
+#define X(NM, NTT)                                                                       \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                 \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_syevd_list<T, NM, NTT>,  \
+                                                         NTT, 0) != hipSuccess)          \
+            nb = 1;                                                                      \
+        return nb > 0 ? nb : 1;                                                          \
+    }
+    BED_SHAPES(X)
+#undef X
+    return 1;
+}
+
+int blocks_per_cu(bed_dtype dt, TeamShape ts)
+{
+    return dt == BED_F32 ? bpc_t<float>(ts) : bpc_t<double>(ts);
+}
+
+}  // namespace bed

@@ -1,0 +1,781 @@
+// bed_syevd.hpp -- one team (a workgroup or a single wave) computes the full
+// eigendecomposition of one symmetric n x n matrix (n <= NMAX <= 64) held in
+// LDS/VGPRs:
+//
+//   load -> Householder tridiagonalization -> rank-one tearing (Sec. 2.1,
+//   Eq. (1)-(3)) -> 2x2 Givens leaves (Sec. 2.2) -> bottom-up merges (Sec. 2.3):
+//   z/sort (Eq. (4)-(5)), deflation, secular roots by hybrid-section + Halley
+//   under bounded interlacing (Eq. (8)-(21)), progressive removal of converged
+//   roots (Eq. (22)), Loewner eigenvectors (Eq. (23)-(25)), back-multiplication
+//   (Eq. (4)) -> Householder back-transform -> sign canonicalization -> store.
+//
+// Team geometry (NT threads, thread t):
+//   Householder / merge GEMM: row r = t % NMAX, column group g = t / NMAX,
+//     CPT = NMAX / G columns per thread (G = NT / NMAX groups).
+//   Per-element phases: wave 0, lane e = element e (n <= 64 fits one wave).
+//   Per-root phases: root q = t / LPR, LPR = NT / NMAX lanes share one root's
+//     pole sums (aligned lane groups, butterfly reductions).
+//   Back-transform: each wave owns NMAX/NW whole columns (no team barrier).
+#pragma once
+
+#include "bed_device.hpp"
+
+namespace bed {
+
+constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
+
+template <typename T, int NMAX, int NT>
+struct Smem {
+    static constexpr int LD = NMAX + 1;  // odd row stride: column walks hit distinct banks
+    static constexpr int NW = NT / 64;
+    static constexpr int G = NT / NMAX;
+    T Q0[NMAX * LD];  // eigenvector blocks (ping)
+    T Q1[NMAX * LD];  // eigenvector blocks (pong)
+    T M[NMAX * LD];   // load staging, merge matrix, output staging
+    T Vt[NMAX * LD];  // reflectors, Vt[k*LD + r] = v_k[r]
+    T a[NMAX], b[NMAX], tau[NMAX];
+    T lam0[NMAX], lam1[NMAX];
+    union {
+        struct {  // Householder
+            T part[2 * G * NMAX];
+            T colb[2 * NMAX];
+            T vbuf[NW * NMAX];
+            T wbuf[NW * NMAX];
+        } h;
+        struct {  // merges
+            T sd[NMAX], sz[NMAX];
+            int sperm[NMAX], sdefl[NMAX];
+            T dk[NMAX], zk[NMAX];
+            int ndpos[NMAX];
+            T rtau[NMAX];
+            int rorg[NMAX];
+            T zh[NMAX], rnrm[NMAX];
+            T itv[NMAX];
+            int itp[NMAX];
+            T rc[NMAX], rs[NMAX];
+            int rpart[NMAX];
+            int col[NMAX];
+            int nk[NMAX];
+            T nrho[NMAX], nzz[NMAX], nfro[NMAX];
+        } m;
+    } u;
+    int bad;
+    int capped;
+    int anyrot;
+};
+
+// Node of a dyadic tearing tree over [0, n): node j at depth d covers
+// [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of >= 3 elements split at
+// the floor of their dyadic midpoint.
+struct Node {
+    int lo, hi, s;
+};
+__device__ __forceinline__ Node node_of(int e, int d, int n)
+{
+    int j = (((e + 1) << d) - 1) / n;
+    Node nd;
+    nd.lo = (j * n) >> d;
+    nd.hi = ((j + 1) * n) >> d;
+    nd.s = ((2 * j + 1) * n) >> (d + 1);
+    return nd;
+}
+
+// 2x2 symmetric Schur decomposition by one Givens/Jacobi rotation (Sec. 2.2).
+template <typename T>
+__device__ __forceinline__ void leaf2(T p, T q, T r, T lam[2], T Q[4])
+{
+    T c = T(1), s = T(0), t = T(0);
+    if (q != T(0)) {
+        T th = (r - p) / (T(2) * q);
+        t = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
+        c = T(1) / f_hypot(T(1), t);
+        s = t * c;
+    }
+    T l1 = p - t * q, l2 = r + t * q;
+    if (l1 <= l2) {
+        lam[0] = l1; lam[1] = l2;
+        Q[0] = c;  Q[1] = s;
+        Q[2] = -s; Q[3] = c;
+    } else {
+        lam[0] = l2; lam[1] = l1;
+        Q[0] = s; Q[1] = c;
+        Q[2] = c; Q[3] = -s;
+    }
+}
+
+// Number of entries of the ascending list x[0..len) that are < v (strict) or
+// <= v (inclusive).
+template <typename T>
+__device__ __forceinline__ int count_below(const T* x, int len, T v, bool inclusive)
+{
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        bool below = inclusive ? (x[mid] <= v) : (x[mid] < v);
+        if (below) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int LPR>
+struct SecVal {
+    T f, f1, f2, eb;
+};
+
+// Secular function Eq. (8) with derivatives Eq. (18), (21), in the shifted
+// variable h = lambda - d_o: delta_i = (d_i - d_o) - h.  Pole sums are split
+// across the LPR lanes of a root's group.
+template <typename T, int LPR>
+__device__ __forceinline__ SecVal<T, LPR> sec_eval(const T* dk, const T* zk, int k, T rho, int o,
+                                                   T h, int sub)
+{
+    T s0 = 0, s1 = 0, s2 = 0, e = 0;
+    const T dorg = dk[o];
+    for (int i = sub; i < k; i += LPR) {
+        T del = (dk[i] - dorg) - h;
+        T rinv = T(1) / del;
+        T zi = zk[i];
+        T t0 = zi * zi * rinv;
+        T t1 = t0 * rinv;
+        s0 += t0;
+        s1 += t1;
+        s2 += t1 * rinv;
+        e += f_abs(t0);
+    }
+    s0 = group_sum<LPR>(s0);
+    s1 = group_sum<LPR>(s1);
+    s2 = group_sum<LPR>(s2);
+    e = group_sum<LPR>(e);
+    SecVal<T, LPR> v;
+    v.f = T(1) + rho * s0;
+    v.f1 = rho * s1;
+    v.f2 = T(2) * rho * s2;
+    v.eb = T(8) * fp<T>::u * (T(1) + rho * e);
+    return v;
+}
+
+template <typename T, int NMAX, int NT>
+__device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict__ lam_out,
+                           T* __restrict__ Q_out, int* __restrict__ info_out,
+                           Smem<T, NMAX, NT>& S, const int t)
+{
+    static_assert(NMAX <= 64 && (NMAX & (NMAX - 1)) == 0, "NMAX: power of two <= 64");
+    static_assert(NT % 64 == 0 && NT >= NMAX && NT % NMAX == 0, "team geometry");
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int NW = NT / 64;
+    constexpr int G = NT / NMAX;
+    constexpr int CPT = NMAX / G;
+    constexpr int LPR = NT / NMAX;
+    const int lane = t & 63, wave = t >> 6;
+    const int r = t % NMAX, g = t / NMAX;
+    const T u = fp<T>::u;
+
+    // ------------------------------------------------------------ load
+    if (t == 0) {
+        S.bad = 0;
+        S.capped = 0;
+    }
+    team_sync<NT>();
+    {
+        bool bad = false;
+        for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+            T v = Ain[e];
+            if (j <= i && !f_finite(v)) bad = true;  // lower triangle only
+            S.M[i * LD + j] = v;
+            j += NT % n;
+            i += NT / n;
+            if (j >= n) {
+                j -= n;
+                ++i;
+            }
+        }
+        if (bad) atomicOr(&S.bad, 1);
+    }
+    team_sync<NT>();
+    if (S.bad) {
+        if (Q_out)
+            for (int e = t; e < n * n; e += NT) Q_out[e] = f_nan<T>();
+        for (int e = t; e < n; e += NT) lam_out[e] = f_nan<T>();
+        if (t == 0 && info_out) *info_out = -1;
+        return;
+    }
+
+    // ------------------------------------------------------------ Householder
+    // Thread (r, g) keeps A[r][g*CPT .. g*CPT+CPT) in registers.  Each step k
+    // uses one team barrier: the partial products of p = A v and the
+    // pre-update pivot column k+1 cross waves together; every wave then forms
+    // w and the next pivot column on its own.
+    {
+        T ar[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+            const int c = g * CPT + j;
+            ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
+        }
+        T xr = (r < n) ? S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
+        T* vb = S.u.h.vbuf + wave * NMAX;
+        T* wb = S.u.h.wbuf + wave * NMAX;
+        const bool elem = lane < NMAX;
+        for (int k = 0; k + 2 < n; ++k) {
+            if (t == k) S.a[k] = xr;
+            const T x0 = __shfl(xr, k + 1);
+            const T sig = wave_sum((elem && r > k + 1) ? xr * xr : T(0));
+            T alpha, tauk, v0;
+            if (sig == T(0)) {
+                alpha = x0;
+                tauk = T(0);
+                v0 = T(1);
+            } else {
+                const T mu = f_sqrt(x0 * x0 + sig);
+                alpha = (x0 < T(0)) ? mu : -mu;
+                v0 = x0 - alpha;
+                tauk = (alpha - x0) / alpha;
+            }
+            const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr / v0 : T(0));
+            if (t == 0) {
+                S.tau[k] = tauk;
+                S.b[k] = alpha;
+            }
+            if (g == 0) S.Vt[k * LD + r] = vr;
+            if (elem) vb[r] = vr;
+            wave_sync();
+            T pp = T(0);
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) pp += ar[j] * vb[g * CPT + j];
+            T* pa = S.u.h.part + (k & 1) * G * NMAX;
+            pa[g * NMAX + r] = pp;
+            {
+                const int c1 = k + 1;
+                if (g == c1 / CPT) {
+                    T val = T(0);
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j)
+                        if (j == c1 - g * CPT) val = ar[j];
+                    S.u.h.colb[(k & 1) * NMAX + r] = val;
+                }
+            }
+            team_sync<NT>();
+            T pr = T(0);
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) pr += pa[gg * NMAX + r];
+            pr *= tauk;
+            const T pv = wave_sum(elem ? pr * vr : T(0));
+            const T wr = pr - T(0.5) * tauk * pv * vr;
+            if (elem) wb[r] = wr;
+            wave_sync();
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = g * CPT + j;
+                ar[j] -= vr * wb[c] + wr * vb[c];
+            }
+            xr = S.u.h.colb[(k & 1) * NMAX + r] - vr * wb[k + 1] - wr * vb[k + 1];
+        }
+        if (n >= 2) {
+            if (t == n - 2) S.a[n - 2] = xr;
+            if (t == n - 1) S.b[n - 2] = xr;
+        }
+        {
+            const int c1 = n - 1;
+            if (g == c1 / CPT && r == c1) {
+                T val = T(0);
+#pragma unroll
+                for (int j = 0; j < CPT; ++j)
+                    if (j == c1 - g * CPT) val = ar[j];
+                S.a[n - 1] = val;
+            }
+        }
+    }
+    team_sync<NT>();
+
+    // ------------------------------------------------------------ tear + leaves
+    int D = 0;
+    while (((n + (1 << D) - 1) >> D) > 2) ++D;
+    T* Qc = S.Q0;
+    T* Qn = S.Q1;
+    T* Lc = S.lam0;
+    T* Ln = S.lam1;
+    if (wave == 0) {
+        const int e = lane;
+        T ae = (e < n) ? S.a[e] : T(0);
+        // Eq. (3): every split s of a node with >= 3 elements subtracts |b_{s-1}|
+        // from a_{s-1} and a_s (ancestors first).
+        for (int d = 0; d < D; ++d) {
+            if (e < n) {
+                Node nd = node_of(e, d, n);
+                if (nd.hi - nd.lo >= 3 && (e == nd.s - 1 || e == nd.s)) ae -= f_abs(S.b[nd.s - 1]);
+            }
+        }
+        int llo = e, lhi = e + 1;
+        if (e < n) {
+            for (int d = 0; d <= D; ++d) {
+                Node nd = node_of(e, d, n);
+                llo = nd.lo;
+                lhi = nd.hi;
+                if (lhi - llo <= 2) break;
+            }
+        }
+        const T a_lo = __shfl(ae, llo);
+        const T a_hi = __shfl(ae, (lhi - llo == 2) ? llo + 1 : llo);
+        if (e < n) {
+            if (lhi - llo == 1) {
+                Lc[e] = ae;
+                Qc[e * LD + e] = T(1);
+            } else {
+                T l2[2], q2[4];
+                leaf2(a_lo, S.b[llo], a_hi, l2, q2);
+                const int rr = e - llo;
+                Lc[e] = l2[rr];
+                Qc[e * LD + llo] = q2[rr * 2 + 0];
+                Qc[e * LD + llo + 1] = q2[rr * 2 + 1];
+            }
+        }
+    }
+    team_sync<NT>();
+
+    // ------------------------------------------------------------ merges
+    for (int d = D - 1; d >= 0; --d) {
+        // ---- M1 (wave 0): z, sort, deflation, compaction -------------------
+        if (wave == 0) {
+            const int e = lane;
+            Node nd = node_of(e < n ? e : 0, d, n);
+            const bool act = (e < n) && (nd.hi - nd.lo >= 3);
+            const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
+            const T bet = act ? S.b[s - 1] : T(0);
+            const T rho = f_abs(bet);
+            const T sgm = (bet < T(0)) ? T(-1) : T(1);
+            if (act) {
+                const T de = Lc[e];
+                const T ze = (e < s) ? sgm * Qc[(s - 1) * LD + e] : Qc[s * LD + e];
+                const int pos = (e < s) ? (e - lo) + count_below(Lc + s, hi - s, de, false)
+                                        : (e - s) + count_below(Lc + lo, s - lo, de, true);
+                S.u.m.sd[lo + pos] = de;
+                S.u.m.sz[lo + pos] = ze;
+                S.u.m.sperm[lo + pos] = e;
+            }
+            wave_sync();
+            T dp = act ? S.u.m.sd[e] : T(0);
+            T zp = act ? S.u.m.sz[e] : T(0);
+            // Frobenius norm of the node (Eq. (10)) from D + rho z z^T, and the
+            // deflation tolerance.
+            const T zz0 = seg_sum(zp * zp, e, lo, hi);
+            const T dz = seg_sum(dp * zp * zp, e, lo, hi);
+            const T d2 = seg_sum(dp * dp, e, lo, hi);
+            const T dmax = seg_max(f_abs(dp), e, lo, hi);
+            const T tol = T(8) * u * f_max(dmax, rho * zz0);
+            const T fro2 = d2 + T(2) * rho * dz + rho * rho * zz0 * zz0;
+            bool defl = act && (rho * f_abs(zp) <= tol);  // type 1
+            if (defl) zp = T(0);
+            // type 2 candidates against the previous non-deflated component
+            const uint64_t live = __ballot(act && !defl);
+            const uint64_t below = live & lane_range(lo, e);
+            const int prev = below ? 63 - __clzll(below) : e;
+            const T zpr = __shfl(zp, prev), dpr = __shfl(dp, prev);
+            bool cand = false;
+            if (act && !defl && prev != e) {
+                const T rr = f_hypot(zpr, zp);
+                const T c = zp / rr, sn = zpr / rr;
+                cand = f_abs((dp - dpr) * c * sn) <= tol;
+            }
+            const uint64_t cmask = __ballot(cand);
+            if (act) {
+                S.u.m.rpart[e] = -1;
+                S.u.m.sdefl[e] = defl ? 1 : 0;
+                S.u.m.sz[e] = zp;
+            }
+            bool hasrot = false;
+            if (cmask) {
+                // Rare path: the exact sequential Givens scan for nodes that
+                // have a type-2 candidate (one lane per such node).
+                wave_sync();
+                const bool mine = act && e == lo && (cmask & lane_range(lo, hi));
+                if (mine) {
+                    int last = -1;
+                    for (int p = lo; p < hi; ++p) {
+                        if (S.u.m.sdefl[p]) continue;
+                        if (last < 0) {
+                            last = p;
+                            continue;
+                        }
+                        const T zl = S.u.m.sz[last], zi = S.u.m.sz[p];
+                        const T dl = S.u.m.sd[last], di = S.u.m.sd[p];
+                        const T rr = f_hypot(zl, zi);
+                        const T c = zi / rr, sn = zl / rr;
+                        if (f_abs((di - dl) * c * sn) <= tol) {
+                            S.u.m.sd[last] = dl * c * c + di * sn * sn;
+                            S.u.m.sd[p] = dl * sn * sn + di * c * c;
+                            S.u.m.sz[last] = T(0);
+                            S.u.m.sz[p] = rr;
+                            S.u.m.sdefl[last] = 1;
+                            S.u.m.rc[last] = c;
+                            S.u.m.rs[last] = sn;
+                            S.u.m.rpart[last] = p;
+                        }
+                        last = p;
+                    }
+                }
+                wave_sync();
+                if (act) {
+                    dp = S.u.m.sd[e];
+                    zp = S.u.m.sz[e];
+                    defl = S.u.m.sdefl[e] != 0;
+                }
+                hasrot = (cmask & lane_range(lo, hi)) != 0;
+            }
+            const uint64_t live2 = __ballot(act && !defl);
+            const uint64_t dead = __ballot(act && defl);
+            const int k = __popcll(live2 & lane_range(lo, hi));
+            const T zz = seg_sum((act && !defl) ? zp * zp : T(0), e, lo, hi);
+            if (act) {
+                if (!defl) {
+                    const int idx = __popcll(live2 & lane_range(lo, e));
+                    S.u.m.dk[lo + idx] = dp;
+                    S.u.m.zk[lo + idx] = zp;
+                    S.u.m.ndpos[lo + idx] = e;
+                } else {
+                    const int idx = k + __popcll(dead & lane_range(lo, e));
+                    S.u.m.itv[lo + idx] = dp;
+                    S.u.m.itp[lo + idx] = e;
+                }
+                if (e == lo) {
+                    S.u.m.nk[lo] = k;
+                    S.u.m.nrho[lo] = rho;
+                    S.u.m.nzz[lo] = zz;
+                    S.u.m.nfro[lo] = f_sqrt(f_max(fro2, T(0)));
+                }
+            }
+            const bool anyrot = __ballot(hasrot) != 0;
+            if (e == 0) S.anyrot = anyrot ? 1 : 0;
+        }
+        team_sync<NT>();
+
+        // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root -----
+        const int q = t / LPR, sub = t % LPR;
+        Node qn = node_of(q < n ? q : 0, d, n);
+        const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
+        const int qlo = qn.lo;
+        const int kq = qact ? S.u.m.nk[qlo] : 0;
+        const int jr = q - qlo;
+        const T* dk = S.u.m.dk + qlo;
+        const T* zk = S.u.m.zk + qlo;
+        const T rho = qact ? S.u.m.nrho[qlo] : T(0);
+        {
+            const bool live = qact && jr < kq;
+            int o = jr, state = 0, nmulti = 0, nhal = 0;
+            bool done = !live, capped = false;
+            T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
+            if (live) {
+                if (jr < kq - 1) {
+                    gap = dk[jr + 1] - dk[jr];
+                    h = T(0.5) * gap;  // Eq. (13): midpoint of the root's own bracket
+                    w0 = gap;
+                    state = 1;
+                } else {
+                    top = rho * S.u.m.nzz[qlo];
+                    const T ubf = S.u.m.nfro[qlo] - dk[jr];  // Eq. (10)-(11)
+                    w0 = top;
+                    if (ubf > T(0) && ubf < top) {
+                        h = ubf;
+                        state = 0;
+                    } else {
+                        h = T(0.5) * top;
+                        state = 1;
+                    }
+                }
+            }
+            // Progressive removal (Eq. (22)): a converged root's lanes idle; the
+            // wave leaves the loop once all of its roots have stopped.
+            while (__ballot(!done)) {
+                if (!done) {
+                    const SecVal<T, LPR> v = sec_eval<T, LPR>(dk, zk, kq, rho, o, h, sub);
+                    if (state == 0) {  // confirm the Frobenius bound
+                        if (v.f >= T(0)) top = h;
+                        w0 = top;
+                        h = T(0.5) * top;
+                        state = 1;
+                    } else if (state == 1 || state == 2) {  // bisection / multi-section
+                        if (v.f == T(0)) {
+                            done = true;
+                        } else {
+                            if (state == 1) {
+                                if (jr < kq - 1) {
+                                    if (v.f > T(0)) {
+                                        L = T(0);
+                                        U = h;
+                                    } else {
+                                        o = jr + 1;  // root nearer d_{j+1}: shift origin
+                                        L = h - gap;
+                                        U = T(0);
+                                    }
+                                } else {
+                                    if (v.f > T(0)) {
+                                        L = T(0);
+                                        U = h;
+                                    } else {
+                                        L = h;
+                                        U = top;
+                                    }
+                                }
+                            } else {
+                                if (v.f > T(0)) U = h;
+                                else L = h;
+                                ++nmulti;
+                            }
+                            if (nmulti < 3 && (U - L) > T(1e-2) * w0) {
+                                // Eq. (16): probe toward the origin pole
+                                h = (o == jr) ? L + T(0.25) * (U - L) : U - T(0.25) * (U - L);
+                                state = 2;
+                            } else {
+                                h = T(0.5) * (L + U);
+                                state = 3;
+                            }
+                        }
+                    } else {  // Halley, Eq. (20), safeguarded by the bracket
+                        if (f_abs(v.f) <= v.eb) {
+                            done = true;
+                        } else {
+                            if (v.f > T(0)) U = h;
+                            else L = h;
+                            if (U - L <= T(2) * u * (f_abs(L) + f_abs(U))) {
+                                done = true;
+                            } else {
+                                const T den = T(2) * v.f1 * v.f1 - v.f * v.f2;
+                                T hn = T(0.5) * (L + U);
+                                if (den > T(0) && f_finite(den)) {
+                                    const T cand = h - T(2) * v.f * v.f1 / den;
+                                    if (cand > L && cand < U) hn = cand;
+                                }
+                                if (hn == h) {
+                                    done = true;
+                                } else {
+                                    h = hn;
+                                    if (++nhal >= SEC_CAP) {
+                                        done = true;
+                                        capped = true;
+                                    }
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            if (live && sub == 0) {
+                S.u.m.rorg[q] = o;
+                S.u.m.rtau[q] = h;
+                if (capped) atomicAdd(&S.capped, 1);
+            }
+        }
+        team_sync<NT>();
+
+        // ---- M3: Loewner zhat (Eq. (25)) as a product of positive ratios -----
+        if (qact && jr < kq) {
+            const T di = dk[jr];
+            T p = T(1);
+            for (int jj = sub; jj < kq; jj += LPR) {
+                const T del = (di - dk[S.u.m.rorg[qlo + jj]]) - S.u.m.rtau[qlo + jj];  // d_i - lam_j
+                p *= (jj == jr) ? (-del / rho) : (-del / (dk[jj] - di));
+            }
+            p = group_prod<LPR>(p);
+            if (sub == 0) S.u.m.zh[q] = f_copysign(f_sqrt(p), zk[jr]);
+        } else {
+            (void)group_prod<LPR>(T(1));
+        }
+        team_sync<NT>();
+
+        // ---- M4: eigenvector norms (Eq. (24)) and output order ---------------
+        {
+            const int mq = qn.hi - qn.lo;
+            if (qact && jr < kq) {
+                const int o = S.u.m.rorg[q];
+                const T tj = S.u.m.rtau[q];
+                T s2 = T(0);
+                for (int ii = sub; ii < kq; ii += LPR) {
+                    const T del = (dk[ii] - dk[o]) - tj;
+                    const T w = S.u.m.zh[qlo + ii] / del;
+                    s2 += w * w;
+                }
+                s2 = group_sum<LPR>(s2);
+                if (sub == 0) S.u.m.rnrm[q] = T(1) / f_sqrt(s2);
+            } else {
+                (void)group_sum<LPR>(T(0));
+            }
+            // rank of item jr among the node's m items (roots, then deflated)
+            if (qact) {
+                const T my = (jr < kq) ? dk[S.u.m.rorg[q]] + S.u.m.rtau[q] : S.u.m.itv[q];
+                int cnt = 0;
+                for (int vv = sub; vv < mq; vv += LPR) {
+                    const T ov = (vv < kq) ? dk[S.u.m.rorg[qlo + vv]] + S.u.m.rtau[qlo + vv]
+                                           : S.u.m.itv[qlo + vv];
+                    cnt += (ov < my || (ov == my && vv < jr)) ? 1 : 0;
+                }
+                cnt = group_sum<LPR>(cnt);
+                if (sub == 0) {
+                    S.u.m.col[q] = qlo + cnt;
+                    Ln[qlo + cnt] = my;
+                }
+            } else {
+                (void)group_sum<LPR>(0);
+            }
+        }
+        team_sync<NT>();
+
+        // ---- M5: merge matrix M = P G (U (+) I), rows in child order ---------
+        if (qact) {
+            const int mq = qn.hi - qn.lo;
+            const int c = S.u.m.col[q];
+            if (jr < kq) {
+                const int o = S.u.m.rorg[q];
+                const T tj = S.u.m.rtau[q];
+                const T nr = S.u.m.rnrm[q];
+                for (int ii = sub; ii < kq; ii += LPR) {
+                    const T del = (dk[ii] - dk[o]) - tj;  // d_i - lam_j
+                    const int row = S.u.m.sperm[S.u.m.ndpos[qlo + ii]];
+                    S.M[row * LD + c] = -S.u.m.zh[qlo + ii] / del * nr;  // zhat_i/(lam_j - d_i)
+                }
+                for (int ii = kq + sub; ii < mq; ii += LPR) {
+                    const int row = S.u.m.sperm[S.u.m.itp[qlo + ii]];
+                    S.M[row * LD + c] = T(0);
+                }
+            } else {
+                const int mypos = S.u.m.itp[q];
+                for (int pp = qlo + sub; pp < qlo + mq; pp += LPR)
+                    S.M[S.u.m.sperm[pp] * LD + c] = (pp == mypos) ? T(1) : T(0);
+            }
+        }
+        team_sync<NT>();
+        if (S.anyrot) {
+            // Type-2 rotations act on the rows of M in reverse scan order.
+            if (qact) {
+                const int c = qlo + jr;
+                if (sub == 0) {
+                    for (int p = qn.hi - 1; p >= qlo; --p) {
+                        const int part = S.u.m.rpart[p];
+                        if (part < 0) continue;
+                        const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
+                        const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
+                        const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
+                        S.M[rp * LD + c] = cc * mp + ss * mi;
+                        S.M[ri * LD + c] = -ss * mp + cc * mi;
+                    }
+                }
+            }
+            team_sync<NT>();
+        }
+
+        // ---- M6: back-multiplication Q_next = blockdiag(Q1, Q2) M (Eq. (4)) --
+        {
+            const Node rn = node_of(r < n ? r : 0, d, n);
+            const bool ract = r < n;
+            const bool merged = ract && (rn.hi - rn.lo >= 3);
+            if (merged) {
+                const int klo = (r < rn.s) ? rn.lo : rn.s;
+                const int khi = (r < rn.s) ? rn.s : rn.hi;
+                T acc[CPT];
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) acc[j] = T(0);
+                for (int kk = klo; kk < khi; ++kk) {
+                    const T av = Qc[r * LD + kk];
+#pragma unroll
+                    for (int j = 0; j < CPT; ++j) acc[j] += av * S.M[kk * LD + g * CPT + j];
+                }
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    const int c = g * CPT + j;
+                    if (c >= rn.lo && c < rn.hi) Qn[r * LD + c] = acc[j];
+                }
+            } else if (ract) {
+                // nodes not merged at this depth keep their block
+#pragma unroll
+                for (int j = 0; j < CPT; ++j) {
+                    const int c = g * CPT + j;
+                    if (c >= rn.lo && c < rn.hi) Qn[r * LD + c] = Qc[r * LD + c];
+                }
+                if (g == 0) Ln[r] = Lc[r];
+            }
+        }
+        team_sync<NT>();
+        T* tq = Qc; Qc = Qn; Qn = tq;
+        T* tl = Lc; Lc = Ln; Ln = tl;
+    }
+
+    if (!Q_out) {  // eigenvalues only
+        for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+        if (t == 0 && info_out) *info_out = S.capped;
+        return;
+    }
+
+    // ------------------------------------------------------------ back-transform
+    // Q_A = H_0 H_1 ... H_{n-3} Q_T.  Wave w owns columns [w*CPW, (w+1)*CPW);
+    // lane l holds rows [h*RPC, (h+1)*RPC) of column w*CPW + l % CPW.
+    {
+        constexpr int CPW = NMAX / NW;
+        constexpr int CH = 64 / CPW;
+        constexpr int RPC = NMAX / CH;
+        static_assert(CPW * NW == NMAX && CH * CPW == 64 && RPC * CH == NMAX, "bt geometry");
+        const int c = wave * CPW + (lane % CPW);
+        const int h = lane / CPW;
+        T qv[RPC];
+#pragma unroll
+        for (int i = 0; i < RPC; ++i) {
+            const int row = h * RPC + i;
+            qv[i] = (row < n && c < n) ? Qc[row * LD + c] : T(0);
+        }
+        for (int k = n - 3; k >= 0; --k) {
+            const T tk = S.tau[k];
+            if (tk == T(0)) continue;
+            T sacc = T(0);
+#pragma unroll
+            for (int i = 0; i < RPC; ++i) sacc += S.Vt[k * LD + h * RPC + i] * qv[i];
+#pragma unroll
+            for (int o = CPW; o < 64; o <<= 1) sacc += __shfl_xor(sacc, o);
+            sacc *= tk;
+#pragma unroll
+            for (int i = 0; i < RPC; ++i) qv[i] -= S.Vt[k * LD + h * RPC + i] * sacc;
+        }
+        // sign canonicalization: largest |.| entry positive, lowest row on ties
+        T best = T(-1);
+        int brow = 1 << 20;
+        T bval = T(0);
+#pragma unroll
+        for (int i = 0; i < RPC; ++i) {
+            const int row = h * RPC + i;
+            const T av = f_abs(qv[i]);
+            if (row < n && (av > best)) {
+                best = av;
+                brow = row;
+                bval = qv[i];
+            }
+        }
+#pragma unroll
+        for (int o = CPW; o < 64; o <<= 1) {
+            const T ob = __shfl_xor(best, o);
+            const int orow = __shfl_xor(brow, o);
+            const T oval = __shfl_xor(bval, o);
+            if (ob > best || (ob == best && orow < brow)) {
+                best = ob;
+                brow = orow;
+                bval = oval;
+            }
+        }
+        const T sgn = (bval < T(0)) ? T(-1) : T(1);
+#pragma unroll
+        for (int i = 0; i < RPC; ++i) {
+            const int row = h * RPC + i;
+            if (row < n && c < n) S.M[row * LD + c] = sgn * qv[i];
+        }
+    }
+    team_sync<NT>();
+    for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+        Q_out[e] = S.M[i * LD + j];
+        j += NT % n;
+        i += NT / n;
+        if (j >= n) {
+            j -= n;
+            ++i;
+        }
+    }
+    for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+    if (t == 0 && info_out) *info_out = S.capped;
+}
+
+}  // namespace bed

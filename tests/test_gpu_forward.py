@@ -1,0 +1,128 @@
+"""GPU parity of the forward solve against the binary64 oracle (through the
+C-ABI library).  Inputs are seeded synthetic workloads; expected values come
+from the oracle at test time."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27325_amd import workloads
+from tests.parity import compare_batch
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts, skipped there
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2604_27325_amd as bed  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def run_gpu(A_np):
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).to(DEV)
+    lam, Q, info = bed.syevd(A, return_info=True)
+    torch.cuda.synchronize()
+    return lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy()
+
+
+def check(A_np, label):
+    dtype = np.float32 if A_np.dtype == np.float32 else np.float64
+    lam_g, Q_g, info = run_gpu(A_np)
+    lam_o, Q_o, info_o = oracle.syevd(A_np.astype(np.float64))
+    worst, fails = compare_batch(A_np, lam_g, Q_g, lam_o, Q_o, dtype, info=info)
+    print(f"[{label}] worst {worst}", flush=True)
+    assert not fails, f"{label}: {len(fails)} failing matrices, first {fails[:3]}"
+    return worst
+
+
+def test_plain_fp64_batch64_n16():
+    check(workloads.plain_fp64(), "plain fp64 64x16")
+
+
+@pytest.mark.parametrize("n", [32, 48, 64])
+def test_paper_scale_fp32_batch512(n):
+    A, planted, _ = workloads.paper_scale(n)
+    check(A, f"paper scale n={n}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 9, 15, 16, 17, 23, 31, 33, 40, 47, 63, 64])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_every_size_class_and_ragged_tail(n, dt):
+    rng = np.random.default_rng(500 + n)
+    A = np.concatenate([workloads.gaussian_sym(rng, 6, n), workloads.covariance(rng, 6, n)])
+    check(A.astype(dt), f"n={n} {dt.__name__}")
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_structured_matrices(dt):
+    n = 37
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal(n)
+    mats = [np.diag(rng.permutation(np.arange(n, dtype=np.float64))),
+            np.eye(n) * 3.0,
+            np.zeros((n, n)),
+            np.outer(u, u),
+            np.diag(np.full(n, 0.5)) + np.diag(np.full(n - 1, -0.3), 1) + np.diag(np.full(n - 1, -0.3), -1)]
+    for i, M in enumerate(mats):
+        check(M[None].astype(dt), f"structured {i} {dt.__name__}")
+
+
+def test_nonfinite_input_reports_info_minus_one():
+    rng = np.random.default_rng(3)
+    A = workloads.gaussian_sym(rng, 4, 20).astype(np.float32)
+    A[1, 5, 2] = np.nan     # lower triangle: detected
+    A[2, 3, 9] = np.inf     # upper triangle: never read
+    lam, Q, info = run_gpu(A)
+    assert list(info) == [0, -1, 0, 0]
+    assert np.all(np.isnan(lam[1])) and np.all(np.isnan(Q[1]))
+    lam_o, Q_o, _ = oracle.syevd(np.tril(A[2]).astype(np.float64))
+    assert np.abs(lam[2] - lam_o).max() < 1e-5 * np.abs(lam_o).max()
+
+
+def test_in_place_and_determinism():
+    rng = np.random.default_rng(4)
+    A_np = workloads.gaussian_sym(rng, 64, 64).astype(np.float32)
+    A = torch.from_numpy(A_np).to(DEV)
+    lam1, Q1 = bed.syevd(A)
+    lam2, Q2 = bed.syevd(A)
+    assert torch.equal(lam1, lam2) and torch.equal(Q1, Q2)  # bitwise repeatable
+    B = A.clone()
+    lam3 = torch.empty(64, 64, device=DEV)
+    bed.syevd_packed([64] * 64, B.view(-1), lam=lam3.view(-1), Q=B.view(-1))  # Q == A
+    assert torch.equal(lam3, lam1) and torch.equal(B, Q1)
+
+
+def test_eigenvalues_only_matches_full():
+    rng = np.random.default_rng(5)
+    A = torch.from_numpy(workloads.covariance(rng, 32, 48).astype(np.float32)).to(DEV)
+    lam, _ = bed.syevd(A)
+    lam2 = bed.syevals(A)
+    assert torch.equal(lam, lam2)
+
+
+def test_uneven_packed_batch_matches_oracle():
+    ns, mats = workloads.uneven(batch=300)
+    ns_, flat = workloads.pack(mats)
+    A = torch.from_numpy(flat).to(DEV)
+    lam, Q, info = bed.syevd_packed(ns, A)
+    torch.cuda.synchronize()
+    lam, Q, info = lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy()
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    offA = offL = 0
+    As, lg, qg, lo, qo = [], [], [], [], []
+    for n in ns:
+        As.append(mats[len(As)])
+        lg.append(lam[offL:offL + n]); lo.append(lam_o[offL:offL + n])
+        qg.append(Q[offA:offA + n * n].reshape(n, n)); qo.append(Q_o[offA:offA + n * n].reshape(n, n))
+        offA += n * n
+        offL += n
+    worst, fails = compare_batch(As, lg, qg, lo, qo, np.float32, info=info)
+    print("[uneven]", worst)
+    assert not fails, fails[:3]
+
+
+def test_batch_zero_is_noop():
+    A = torch.empty(0, device=DEV)
+    lam, Q, info = bed.syevd_packed([], A)
+    assert lam.numel() == 0 and Q.numel() == 0
