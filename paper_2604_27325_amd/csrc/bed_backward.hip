@@ -23,7 +23,7 @@ struct BwdSmem {
 };
 
 template <typename T, int NMAX, int NT>
-__device__ void bwd_team(const T *__restrict__ lam, const T *__restrict__ Q,
+__device__ __forceinline__ void bwd_team(const T *__restrict__ lam, const T *__restrict__ Q,
                          const T *__restrict__ dlam, const T *__restrict__ dQ, T *__restrict__ dA,
                          const int n, const T eps, BwdSmem<T, NMAX> &S, const int t)
 {

@@ -1,9 +1,10 @@
 // bed_device.hpp -- wave-level helpers for gfx950 (CDNA4, wave64).
 //
-// All cross-lane traffic inside a wave goes through ds_bpermute/DPP (via the
-// HIP shuffle intrinsics); cross-wave traffic goes through LDS plus a
-// workgroup barrier.  A "team" is the set of threads that cooperate on one
-// matrix: a whole workgroup (NT > 64) or a single wave (NT == 64).
+// Cross-lane traffic inside a wave uses DPP (quad permutes, row mirrors) and
+// the gfx950 permlane16/permlane32 swaps -- plain VALU operations, no LDS
+// round trip.  Cross-wave traffic goes through LDS plus a workgroup barrier.
+// A "team" is the set of threads that cooperate on one matrix: a whole
+// workgroup (NT > 64) or a single wave (NT == 64).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,8 +22,6 @@ template <> struct fp<double> {
 
 __device__ __forceinline__ float f_abs(float x) { return fabsf(x); }
 __device__ __forceinline__ double f_abs(double x) { return fabs(x); }
-__device__ __forceinline__ float f_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float f_hypot(float x, float y) { return hypotf(x, y); }
 __device__ __forceinline__ double f_hypot(double x, double y) { return hypot(x, y); }
 __device__ __forceinline__ float f_max(float x, float y) { return fmaxf(x, y); }
@@ -34,6 +33,15 @@ __device__ __forceinline__ bool f_finite(double x) { return isfinite(x); }
 template <typename T> __device__ __forceinline__ T f_nan();
 template <> __device__ __forceinline__ float f_nan<float>() { return __builtin_nanf(""); }
 template <> __device__ __forceinline__ double f_nan<double>() { return __builtin_nan(""); }
+
+// binary32: the hardware reciprocal / square root (about 1 ulp); binary64:
+// IEEE division and square root.
+__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float f_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double f_div(double a, double b) { return a / b; }
 
 // Orders LDS traffic between the lanes of one wave: a wave executes its LDS
 // instructions in order, so only compiler reordering has to be prevented.
@@ -53,25 +61,122 @@ __device__ __forceinline__ void team_sync()
         wave_sync();
 }
 
-template <typename T> __device__ __forceinline__ T wave_sum(T x)
+// ---- cross-lane moves --------------------------------------------------------
+// DPP controls: quad_perm [1,0,3,2] = 0xB1 (lane ^ 1), [2,3,0,1] = 0x4E
+// (lane ^ 2), row_half_mirror = 0x141 (lane ^ 7 within 8), row_mirror = 0x140
+// (lane ^ 15 within 16).
+template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t x)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)x, CTRL, 0xF, 0xF, false);
+}
+// Value of lane ^ 16 (permlane16_swap exchanges odd rows of its first operand
+// with even rows of its second) and of lane ^ 32 (permlane32_swap exchanges the
+// upper half of its first operand with the lower half of its second).
+__device__ __forceinline__ uint32_t xor16_32(uint32_t x, int lane)
+{
+    auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return ((lane >> 4) & 1) ? p[0] : p[1];
+}
+__device__ __forceinline__ uint32_t xor32_32(uint32_t x, int lane)
+{
+    auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (lane >= 32) ? p[0] : p[1];
 }
 
-// Sum / product over aligned groups of W consecutive lanes (W a power of two
-// dividing 64).  Butterfly order makes every lane of a group bit-identical.
-template <int W, typename T> __device__ __forceinline__ T group_sum(T x)
+// Generic "value held by lane ^ MASK-pattern" for float / double / int.
+template <int STEP> __device__ __forceinline__ uint32_t xmove32(uint32_t x, int lane)
 {
-#pragma unroll
-    for (int o = W / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    if constexpr (STEP == 1) return dpp32<0xB1>(x);
+    else if constexpr (STEP == 2) return dpp32<0x4E>(x);
+    else if constexpr (STEP == 4) return dpp32<0x141>(x);
+    else if constexpr (STEP == 8) return dpp32<0x140>(x);
+    else if constexpr (STEP == 16) return xor16_32(x, lane);
+    else return xor32_32(x, lane);
+}
+template <int STEP> __device__ __forceinline__ float xmove(float x, int lane)
+{
+    return __uint_as_float(xmove32<STEP>(__float_as_uint(x), lane));
+}
+template <int STEP> __device__ __forceinline__ int xmove(int x, int lane)
+{
+    return (int)xmove32<STEP>((uint32_t)x, lane);
+}
+template <int STEP> __device__ __forceinline__ double xmove(double x, int lane)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = xmove32<STEP>((uint32_t)b, lane);
+    const uint32_t hi = xmove32<STEP>((uint32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum / product / max over aligned groups of W consecutive lanes (W a power of
+// two).  The partner pattern is a butterfly (xor 1, 2, then mirrors inside
+// 8/16 lanes, then row swaps), so every lane of a group gets a bit-identical
+// result.
+template <int W, typename T> __device__ __forceinline__ T group_sum(T x, int lane)
+{
+    if constexpr (W >= 2) x += xmove<1>(x, lane);
+    if constexpr (W >= 4) x += xmove<2>(x, lane);
+    if constexpr (W >= 8) x += xmove<4>(x, lane);
+    if constexpr (W >= 16) x += xmove<8>(x, lane);
+    if constexpr (W >= 32) x += xmove<16>(x, lane);
+    if constexpr (W >= 64) x += xmove<32>(x, lane);
     return x;
 }
-template <int W, typename T> __device__ __forceinline__ T group_prod(T x)
+template <int W, typename T> __device__ __forceinline__ T group_prod(T x, int lane)
 {
-#pragma unroll
-    for (int o = W / 2; o >= 1; o >>= 1) x *= __shfl_xor(x, o);
+    if constexpr (W >= 2) x *= xmove<1>(x, lane);
+    if constexpr (W >= 4) x *= xmove<2>(x, lane);
+    if constexpr (W >= 8) x *= xmove<4>(x, lane);
+    if constexpr (W >= 16) x *= xmove<8>(x, lane);
+    if constexpr (W >= 32) x *= xmove<16>(x, lane);
+    if constexpr (W >= 64) x *= xmove<32>(x, lane);
+    return x;
+}
+template <typename T> __device__ __forceinline__ T wave_sum(T x, int lane)
+{
+    return group_sum<64>(x, lane);
+}
+
+// Broadcast of one lane's value to the whole wave (lane index uniform).
+__device__ __forceinline__ float bcast(float x, int src)
+{
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(x), src));
+}
+__device__ __forceinline__ double bcast(double x, int src)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ int bcast(int x, int src) { return __builtin_amdgcn_readlane(x, src); }
+
+// Inclusive prefix sum over the 64 lanes of a wave (row shifts, then the two
+// row broadcasts), no LDS.
+template <int CTRL, int ROWMASK> __device__ __forceinline__ uint32_t dppm32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)x, CTRL, ROWMASK, 0xF, true);
+}
+template <int CTRL, int ROWMASK> __device__ __forceinline__ float dppm(float x)
+{
+    return __uint_as_float(dppm32<CTRL, ROWMASK>(__float_as_uint(x)));
+}
+template <int CTRL, int ROWMASK> __device__ __forceinline__ double dppm(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = dppm32<CTRL, ROWMASK>((uint32_t)b);
+    const uint32_t hi = dppm32<CTRL, ROWMASK>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <typename T> __device__ __forceinline__ T wave_prefix_sum(T x)
+{
+    x += dppm<0x111, 0xF>(x);  // row_shr:1 (out-of-row sources read 0)
+    x += dppm<0x112, 0xF>(x);  // row_shr:2
+    x += dppm<0x114, 0xF>(x);  // row_shr:4
+    x += dppm<0x118, 0xF>(x);  // row_shr:8
+    x += dppm<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dppm<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return x;
 }
 
@@ -81,28 +186,6 @@ __device__ __forceinline__ uint64_t lane_range(int lo, int hi)
     uint64_t up = (hi >= 64) ? ~0ull : ((1ull << hi) - 1ull);
     uint64_t dn = (lo >= 64) ? ~0ull : ((1ull << lo) - 1ull);
     return up & ~dn;
-}
-
-// Segmented inclusive scan over contiguous lane segments [lo, hi); returns
-// the segment total to every lane of the segment.  Every lane of the wave
-// must call it (lanes outside any segment pass lo = hi = lane, x = 0).
-template <typename T> __device__ __forceinline__ T seg_sum(T x, int e, int lo, int hi)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T y = __shfl_up(x, o);
-        if (e - o >= lo) x += y;
-    }
-    return __shfl(x, hi > lo ? hi - 1 : e);
-}
-template <typename T> __device__ __forceinline__ T seg_max(T x, int e, int lo, int hi)
-{
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T y = __shfl_up(x, o);
-        if (e - o >= lo) x = f_max(x, y);
-    }
-    return __shfl(x, hi > lo ? hi - 1 : e);
 }
 
 }  // namespace bed

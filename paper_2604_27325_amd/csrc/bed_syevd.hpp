@@ -20,6 +20,15 @@
 
 #include "bed_device.hpp"
 
+// Phase markers: no-ops in the library; a profiling build may define
+// BED_PHASE(id) to timestamp the phases of one team.
+#ifndef BED_PHASE
+#define BED_PHASE(id) ((void)0)
+#endif
+#ifndef BED_COUNT
+#define BED_COUNT(id, value) ((void)0)
+#endif
+
 namespace bed {
 
 constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
@@ -32,26 +41,25 @@ struct Smem {
     T Q0[NMAX * LD];  // eigenvector blocks (ping)
     T Q1[NMAX * LD];  // eigenvector blocks (pong)
     T M[NMAX * LD];   // load staging, merge matrix, output staging
-    T Vt[NMAX * LD];  // reflectors, Vt[k*LD + r] = v_k[r]
+    alignas(16) T Vt[NMAX * NMAX];  // reflector k in row k: Vt[k*NMAX + r] = v_k[r]
     T a[NMAX], b[NMAX], tau[NMAX];
     T lam0[NMAX], lam1[NMAX];
     union {
         struct {  // Householder
             T part[2 * G * NMAX];
             T colb[2 * NMAX];
-            T vbuf[NW * NMAX];
-            T wbuf[NW * NMAX];
+            alignas(16) T vbuf[NW * NMAX];
+            alignas(16) T wbuf[NW * NMAX];
         } h;
-        struct {  // merges
-            T sd[NMAX], sz[NMAX];
+        struct {  // merges; arrays indexed by global position (node-local at [lo, hi))
+            T sd[NMAX], sz[NMAX];     // sorted poles / weights (deflation in place)
             int sperm[NMAX], sdefl[NMAX];
-            T dk[NMAX], zk[NMAX];
-            int ndpos[NMAX];
-            T rtau[NMAX];
-            int rorg[NMAX];
+            T dk[NMAX], zk[NMAX];     // non-deflated poles / weights at [lo, lo + k)
+            int ndrow[NMAX];          // child-order row of non-deflated component
+            int itrow[NMAX];          // child-order row of deflated item at [lo + k, hi)
+            T itv[NMAX];              // item values: roots at [lo, lo+k), deflated after
+            T rtau[NMAX], rdo[NMAX];  // root offset and its origin pole value
             T zh[NMAX], rnrm[NMAX];
-            T itv[NMAX];
-            int itp[NMAX];
             T rc[NMAX], rs[NMAX];
             int rpart[NMAX];
             int col[NMAX];
@@ -118,7 +126,21 @@ __device__ __forceinline__ int count_below(const T* x, int len, T v, bool inclus
     return lo;
 }
 
-template <typename T, int LPR>
+// Uniform index into a register array without dynamic VGPR indexing: a
+// log-depth chain of selects (idx is wave-uniform in every caller).
+template <int N, typename T>
+__device__ __forceinline__ T pick(const T* a, int idx)
+{
+    if constexpr (N == 1) {
+        return a[0];
+    } else {
+        const T lo = pick<N / 2>(a, idx);
+        const T hi = pick<N / 2>(a + N / 2, idx);
+        return (idx & (N / 2)) ? hi : lo;
+    }
+}
+
+template <typename T>
 struct SecVal {
     T f, f1, f2, eb;
 };
@@ -127,27 +149,26 @@ struct SecVal {
 // variable h = lambda - d_o: delta_i = (d_i - d_o) - h.  Pole sums are split
 // across the LPR lanes of a root's group.
 template <typename T, int LPR>
-__device__ __forceinline__ SecVal<T, LPR> sec_eval(const T* dk, const T* zk, int k, T rho, int o,
-                                                   T h, int sub)
+__device__ __forceinline__ SecVal<T> sec_eval(const T* dk, const T* zk, int k, T rho, T dorg, T h,
+                                              int sub, int lane)
 {
     T s0 = 0, s1 = 0, s2 = 0, e = 0;
-    const T dorg = dk[o];
     for (int i = sub; i < k; i += LPR) {
-        T del = (dk[i] - dorg) - h;
-        T rinv = T(1) / del;
-        T zi = zk[i];
-        T t0 = zi * zi * rinv;
-        T t1 = t0 * rinv;
+        const T del = (dk[i] - dorg) - h;
+        const T rinv = f_rcp(del);
+        const T zi = zk[i];
+        const T t0 = zi * zi * rinv;
+        const T t1 = t0 * rinv;
         s0 += t0;
         s1 += t1;
         s2 += t1 * rinv;
         e += f_abs(t0);
     }
-    s0 = group_sum<LPR>(s0);
-    s1 = group_sum<LPR>(s1);
-    s2 = group_sum<LPR>(s2);
-    e = group_sum<LPR>(e);
-    SecVal<T, LPR> v;
+    s0 = group_sum<LPR>(s0, lane);
+    s1 = group_sum<LPR>(s1, lane);
+    s2 = group_sum<LPR>(s2, lane);
+    e = group_sum<LPR>(e, lane);
+    SecVal<T> v;
     v.f = T(1) + rho * s0;
     v.f1 = rho * s1;
     v.f2 = T(2) * rho * s2;
@@ -156,9 +177,10 @@ __device__ __forceinline__ SecVal<T, LPR> sec_eval(const T* dk, const T* zk, int
 }
 
 template <typename T, int NMAX, int NT>
-__device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict__ lam_out,
-                           T* __restrict__ Q_out, int* __restrict__ info_out,
-                           Smem<T, NMAX, NT>& S, const int t)
+__device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int n,
+                                           T* __restrict__ lam_out, T* __restrict__ Q_out,
+                                           int* __restrict__ info_out, Smem<T, NMAX, NT>& S,
+                                           const int t)
 {
     static_assert(NMAX <= 64 && (NMAX & (NMAX - 1)) == 0, "NMAX: power of two <= 64");
     static_assert(NT % 64 == 0 && NT >= NMAX && NT % NMAX == 0, "team geometry");
@@ -167,10 +189,12 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
     constexpr int G = NT / NMAX;
     constexpr int CPT = NMAX / G;
     constexpr int LPR = NT / NMAX;
-    const int lane = t & 63, wave = t >> 6;
+    const int lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int r = t % NMAX, g = t / NMAX;
     const T u = fp<T>::u;
 
+    BED_PHASE(0);
     // ------------------------------------------------------------ load
     if (t == 0) {
         S.bad = 0;
@@ -200,12 +224,13 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
         if (t == 0 && info_out) *info_out = -1;
         return;
     }
+    BED_PHASE(1);
 
     // ------------------------------------------------------------ Householder
     // Thread (r, g) keeps A[r][g*CPT .. g*CPT+CPT) in registers.  Each step k
     // uses one team barrier: the partial products of p = A v and the
     // pre-update pivot column k+1 cross waves together; every wave then forms
-    // w and the next pivot column on its own.
+    // w and the next pivot column on its own (a look-ahead of one column).
     {
         T ar[CPT];
 #pragma unroll
@@ -214,62 +239,60 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
         }
         T xr = (r < n) ? S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
-        T* vb = S.u.h.vbuf + wave * NMAX;
-        T* wb = S.u.h.wbuf + wave * NMAX;
         const bool elem = lane < NMAX;
         for (int k = 0; k + 2 < n; ++k) {
             if (t == k) S.a[k] = xr;
-            const T x0 = __shfl(xr, k + 1);
-            const T sig = wave_sum((elem && r > k + 1) ? xr * xr : T(0));
-            T alpha, tauk, v0;
+            const T x0 = bcast(xr, k + 1);
+            const T sig = wave_sum((elem && r > k + 1) ? xr * xr : T(0), lane);
+            T alpha, tauk, rv0;
             if (sig == T(0)) {
                 alpha = x0;
                 tauk = T(0);
-                v0 = T(1);
+                rv0 = T(1);
             } else {
                 const T mu = f_sqrt(x0 * x0 + sig);
                 alpha = (x0 < T(0)) ? mu : -mu;
-                v0 = x0 - alpha;
-                tauk = (alpha - x0) / alpha;
+                rv0 = f_rcp(x0 - alpha);
+                tauk = f_div(alpha - x0, alpha);
             }
-            const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr / v0 : T(0));
+            const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr * rv0 : T(0));
             if (t == 0) {
                 S.tau[k] = tauk;
                 S.b[k] = alpha;
             }
-            if (g == 0) S.Vt[k * LD + r] = vr;
+            if (g == 0) S.Vt[k * NMAX + r] = vr;
+            // v of this thread's column group through the wave's LDS buffer
+            T* vb = S.u.h.vbuf + wave * NMAX;
             if (elem) vb[r] = vr;
             wave_sync();
+            T vc[CPT];
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) vc[j] = vb[g * CPT + j];
             T pp = T(0);
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) pp += ar[j] * vb[g * CPT + j];
+            for (int j = 0; j < CPT; ++j) pp = fma(ar[j], vc[j], pp);
             T* pa = S.u.h.part + (k & 1) * G * NMAX;
             pa[g * NMAX + r] = pp;
             {
                 const int c1 = k + 1;
-                if (g == c1 / CPT) {
-                    T val = T(0);
-#pragma unroll
-                    for (int j = 0; j < CPT; ++j)
-                        if (j == c1 - g * CPT) val = ar[j];
-                    S.u.h.colb[(k & 1) * NMAX + r] = val;
-                }
+                if (g == c1 / CPT) S.u.h.colb[(k & 1) * NMAX + r] = pick<CPT>(ar, c1 - g * CPT);
             }
             team_sync<NT>();
             T pr = T(0);
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) pr += pa[gg * NMAX + r];
             pr *= tauk;
-            const T pv = wave_sum(elem ? pr * vr : T(0));
+            const T pv = wave_sum(elem ? pr * vr : T(0), lane);
             const T wr = pr - T(0.5) * tauk * pv * vr;
+            T* wb = S.u.h.wbuf + wave * NMAX;
             if (elem) wb[r] = wr;
             wave_sync();
 #pragma unroll
             for (int j = 0; j < CPT; ++j) {
-                const int c = g * CPT + j;
-                ar[j] -= vr * wb[c] + wr * vb[c];
+                const T wc = wb[g * CPT + j];
+                ar[j] = fma(-wr, vc[j], fma(-vr, wc, ar[j]));
             }
-            xr = S.u.h.colb[(k & 1) * NMAX + r] - vr * wb[k + 1] - wr * vb[k + 1];
+            xr = fma(-wr, vb[k + 1], fma(-vr, wb[k + 1], S.u.h.colb[(k & 1) * NMAX + r]));
         }
         if (n >= 2) {
             if (t == n - 2) S.a[n - 2] = xr;
@@ -277,16 +300,14 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
         }
         {
             const int c1 = n - 1;
-            if (g == c1 / CPT && r == c1) {
-                T val = T(0);
-#pragma unroll
-                for (int j = 0; j < CPT; ++j)
-                    if (j == c1 - g * CPT) val = ar[j];
-                S.a[n - 1] = val;
+            if (g == c1 / CPT) {
+                const T val = pick<CPT>(ar, c1 - g * CPT);
+                if (r == c1) S.a[n - 1] = val;
             }
         }
     }
     team_sync<NT>();
+    BED_PHASE(2);
 
     // ------------------------------------------------------------ tear + leaves
     int D = 0;
@@ -315,30 +336,31 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
                 if (lhi - llo <= 2) break;
             }
         }
-        const T a_lo = __shfl(ae, llo);
-        const T a_hi = __shfl(ae, (lhi - llo == 2) ? llo + 1 : llo);
+        if (e < n) S.a[e] = ae;  // torn diagonal
+        wave_sync();
         if (e < n) {
             if (lhi - llo == 1) {
                 Lc[e] = ae;
                 Qc[e * LD + e] = T(1);
             } else {
                 T l2[2], q2[4];
-                leaf2(a_lo, S.b[llo], a_hi, l2, q2);
-                const int rr = e - llo;
-                Lc[e] = l2[rr];
-                Qc[e * LD + llo] = q2[rr * 2 + 0];
-                Qc[e * LD + llo + 1] = q2[rr * 2 + 1];
+                leaf2(S.a[llo], S.b[llo], S.a[llo + 1], l2, q2);
+                const bool second = e != llo;
+                Lc[e] = second ? l2[1] : l2[0];
+                Qc[e * LD + llo] = second ? q2[2] : q2[0];
+                Qc[e * LD + llo + 1] = second ? q2[3] : q2[1];
             }
         }
     }
     team_sync<NT>();
+    BED_PHASE(3);
 
     // ------------------------------------------------------------ merges
     for (int d = D - 1; d >= 0; --d) {
         // ---- M1 (wave 0): z, sort, deflation, compaction -------------------
         if (wave == 0) {
             const int e = lane;
-            Node nd = node_of(e < n ? e : 0, d, n);
+            const Node nd = node_of(e < n ? e : 0, d, n);
             const bool act = (e < n) && (nd.hi - nd.lo >= 3);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
             const T bet = act ? S.b[s - 1] : T(0);
@@ -356,13 +378,18 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             wave_sync();
             T dp = act ? S.u.m.sd[e] : T(0);
             T zp = act ? S.u.m.sz[e] : T(0);
-            // Frobenius norm of the node (Eq. (10)) from D + rho z z^T, and the
-            // deflation tolerance.
-            const T zz0 = seg_sum(zp * zp, e, lo, hi);
-            const T dz = seg_sum(dp * zp * zp, e, lo, hi);
-            const T d2 = seg_sum(dp * dp, e, lo, hi);
-            const T dmax = seg_max(f_abs(dp), e, lo, hi);
+            // node sums over [lo, hi) from wave prefix sums: z^T z, d^T (z o z),
+            // d^T d; max |d| from the sorted end points
+            const T pz = wave_prefix_sum(zp * zp);
+            const T pdz = wave_prefix_sum(dp * zp * zp);
+            const T pd2 = wave_prefix_sum(dp * dp);
+            const int ilo = (lo > 0) ? lo - 1 : 0, ihi = (hi > lo) ? hi - 1 : e;
+            const T zz0 = __shfl(pz, ihi) - (lo > 0 ? __shfl(pz, ilo) : T(0));
+            const T dz = __shfl(pdz, ihi) - (lo > 0 ? __shfl(pdz, ilo) : T(0));
+            const T d2 = __shfl(pd2, ihi) - (lo > 0 ? __shfl(pd2, ilo) : T(0));
+            const T dmax = act ? f_max(f_abs(S.u.m.sd[lo]), f_abs(S.u.m.sd[hi - 1])) : T(0);
             const T tol = T(8) * u * f_max(dmax, rho * zz0);
+            // Frobenius norm of the node (Eq. (10)), from D + rho z z^T
             const T fro2 = d2 + T(2) * rho * dz + rho * rho * zz0 * zz0;
             bool defl = act && (rho * f_abs(zp) <= tol);  // type 1
             if (defl) zp = T(0);
@@ -425,33 +452,36 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             const uint64_t live2 = __ballot(act && !defl);
             const uint64_t dead = __ballot(act && defl);
             const int k = __popcll(live2 & lane_range(lo, hi));
-            const T zz = seg_sum((act && !defl) ? zp * zp : T(0), e, lo, hi);
             if (act) {
+                const int row = S.u.m.sperm[e];
                 if (!defl) {
                     const int idx = __popcll(live2 & lane_range(lo, e));
                     S.u.m.dk[lo + idx] = dp;
                     S.u.m.zk[lo + idx] = zp;
-                    S.u.m.ndpos[lo + idx] = e;
+                    S.u.m.ndrow[lo + idx] = row;
                 } else {
                     const int idx = k + __popcll(dead & lane_range(lo, e));
                     S.u.m.itv[lo + idx] = dp;
-                    S.u.m.itp[lo + idx] = e;
+                    S.u.m.itrow[lo + idx] = row;
                 }
-                if (e == lo) {
-                    S.u.m.nk[lo] = k;
-                    S.u.m.nrho[lo] = rho;
-                    S.u.m.nzz[lo] = zz;
-                    S.u.m.nfro[lo] = f_sqrt(f_max(fro2, T(0)));
-                }
+            }
+            const T pzz = wave_prefix_sum((act && !defl) ? zp * zp : T(0));
+            const T zz = __shfl(pzz, ihi) - (lo > 0 ? __shfl(pzz, ilo) : T(0));
+            if (act && e == lo) {
+                S.u.m.nk[lo] = k;
+                S.u.m.nrho[lo] = rho;
+                S.u.m.nzz[lo] = zz;
+                S.u.m.nfro[lo] = f_sqrt(f_max(fro2, T(0)));
             }
             const bool anyrot = __ballot(hasrot) != 0;
             if (e == 0) S.anyrot = anyrot ? 1 : 0;
         }
         team_sync<NT>();
+        BED_PHASE(10 + 8 * d + 0);
 
         // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root -----
         const int q = t / LPR, sub = t % LPR;
-        Node qn = node_of(q < n ? q : 0, d, n);
+        const Node qn = node_of(q < n ? q : 0, d, n);
         const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
         const int qlo = qn.lo;
         const int kq = qact ? S.u.m.nk[qlo] : 0;
@@ -464,6 +494,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             int o = jr, state = 0, nmulti = 0, nhal = 0;
             bool done = !live, capped = false;
             T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
+            T dorg = live ? dk[jr] : T(0);
             if (live) {
                 if (jr < kq - 1) {
                     gap = dk[jr + 1] - dk[jr];
@@ -485,9 +516,11 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             }
             // Progressive removal (Eq. (22)): a converged root's lanes idle; the
             // wave leaves the loop once all of its roots have stopped.
+            int rounds = 0;
             while (__ballot(!done)) {
+                ++rounds;
                 if (!done) {
-                    const SecVal<T, LPR> v = sec_eval<T, LPR>(dk, zk, kq, rho, o, h, sub);
+                    const SecVal<T> v = sec_eval<T, LPR>(dk, zk, kq, rho, dorg, h, sub, lane);
                     if (state == 0) {  // confirm the Frobenius bound
                         if (v.f >= T(0)) top = h;
                         w0 = top;
@@ -504,6 +537,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
                                         U = h;
                                     } else {
                                         o = jr + 1;  // root nearer d_{j+1}: shift origin
+                                        dorg = dk[jr + 1];
                                         L = h - gap;
                                         U = T(0);
                                     }
@@ -542,7 +576,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
                                 const T den = T(2) * v.f1 * v.f1 - v.f * v.f2;
                                 T hn = T(0.5) * (L + U);
                                 if (den > T(0) && f_finite(den)) {
-                                    const T cand = h - T(2) * v.f * v.f1 / den;
+                                    const T cand = h - T(2) * v.f * v.f1 * f_rcp(den);
                                     if (cand > L && cand < U) hn = cand;
                                 }
                                 if (hn == h) {
@@ -559,108 +593,101 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
                     }
                 }
             }
+            BED_COUNT(d, rounds);
             if (live && sub == 0) {
-                S.u.m.rorg[q] = o;
+                S.u.m.rdo[q] = dorg;
                 S.u.m.rtau[q] = h;
+                S.u.m.itv[q] = dorg + h;
                 if (capped) atomicAdd(&S.capped, 1);
             }
         }
         team_sync<NT>();
+        BED_PHASE(10 + 8 * d + 1);
 
         // ---- M3: Loewner zhat (Eq. (25)) as a product of positive ratios -----
         if (qact && jr < kq) {
             const T di = dk[jr];
             T p = T(1);
             for (int jj = sub; jj < kq; jj += LPR) {
-                const T del = (di - dk[S.u.m.rorg[qlo + jj]]) - S.u.m.rtau[qlo + jj];  // d_i - lam_j
+                const T del = (di - S.u.m.rdo[qlo + jj]) - S.u.m.rtau[qlo + jj];  // d_i - lam_j
                 p *= (jj == jr) ? (-del / rho) : (-del / (dk[jj] - di));
             }
-            p = group_prod<LPR>(p);
+            p = group_prod<LPR>(p, lane);
             if (sub == 0) S.u.m.zh[q] = f_copysign(f_sqrt(p), zk[jr]);
-        } else {
-            (void)group_prod<LPR>(T(1));
         }
         team_sync<NT>();
+        BED_PHASE(10 + 8 * d + 2);
 
         // ---- M4: eigenvector norms (Eq. (24)) and output order ---------------
         {
             const int mq = qn.hi - qn.lo;
             if (qact && jr < kq) {
-                const int o = S.u.m.rorg[q];
+                const T dorg = S.u.m.rdo[q];
                 const T tj = S.u.m.rtau[q];
                 T s2 = T(0);
                 for (int ii = sub; ii < kq; ii += LPR) {
-                    const T del = (dk[ii] - dk[o]) - tj;
-                    const T w = S.u.m.zh[qlo + ii] / del;
+                    const T w = S.u.m.zh[qlo + ii] * f_rcp((dk[ii] - dorg) - tj);
                     s2 += w * w;
                 }
-                s2 = group_sum<LPR>(s2);
-                if (sub == 0) S.u.m.rnrm[q] = T(1) / f_sqrt(s2);
-            } else {
-                (void)group_sum<LPR>(T(0));
+                s2 = group_sum<LPR>(s2, lane);
+                if (sub == 0) S.u.m.rnrm[q] = f_rcp(f_sqrt(s2));
             }
             // rank of item jr among the node's m items (roots, then deflated)
             if (qact) {
-                const T my = (jr < kq) ? dk[S.u.m.rorg[q]] + S.u.m.rtau[q] : S.u.m.itv[q];
+                const T my = S.u.m.itv[q];
                 int cnt = 0;
                 for (int vv = sub; vv < mq; vv += LPR) {
-                    const T ov = (vv < kq) ? dk[S.u.m.rorg[qlo + vv]] + S.u.m.rtau[qlo + vv]
-                                           : S.u.m.itv[qlo + vv];
+                    const T ov = S.u.m.itv[qlo + vv];
                     cnt += (ov < my || (ov == my && vv < jr)) ? 1 : 0;
                 }
-                cnt = group_sum<LPR>(cnt);
+                cnt = group_sum<LPR>(cnt, lane);
                 if (sub == 0) {
                     S.u.m.col[q] = qlo + cnt;
                     Ln[qlo + cnt] = my;
                 }
-            } else {
-                (void)group_sum<LPR>(0);
             }
         }
         team_sync<NT>();
+        BED_PHASE(10 + 8 * d + 3);
 
         // ---- M5: merge matrix M = P G (U (+) I), rows in child order ---------
         if (qact) {
             const int mq = qn.hi - qn.lo;
             const int c = S.u.m.col[q];
             if (jr < kq) {
-                const int o = S.u.m.rorg[q];
+                const T dorg = S.u.m.rdo[q];
                 const T tj = S.u.m.rtau[q];
                 const T nr = S.u.m.rnrm[q];
                 for (int ii = sub; ii < kq; ii += LPR) {
-                    const T del = (dk[ii] - dk[o]) - tj;  // d_i - lam_j
-                    const int row = S.u.m.sperm[S.u.m.ndpos[qlo + ii]];
-                    S.M[row * LD + c] = -S.u.m.zh[qlo + ii] / del * nr;  // zhat_i/(lam_j - d_i)
+                    const T del = (dk[ii] - dorg) - tj;  // d_i - lam_j
+                    S.M[S.u.m.ndrow[qlo + ii] * LD + c] = -S.u.m.zh[qlo + ii] * nr * f_rcp(del);
                 }
-                for (int ii = kq + sub; ii < mq; ii += LPR) {
-                    const int row = S.u.m.sperm[S.u.m.itp[qlo + ii]];
-                    S.M[row * LD + c] = T(0);
-                }
+                for (int ii = kq + sub; ii < mq; ii += LPR)
+                    S.M[S.u.m.itrow[qlo + ii] * LD + c] = T(0);
             } else {
-                const int mypos = S.u.m.itp[q];
-                for (int pp = qlo + sub; pp < qlo + mq; pp += LPR)
-                    S.M[S.u.m.sperm[pp] * LD + c] = (pp == mypos) ? T(1) : T(0);
+                const int myrow = S.u.m.itrow[q];
+                for (int row = qlo + sub; row < qlo + mq; row += LPR)
+                    S.M[row * LD + c] = (row == myrow) ? T(1) : T(0);
             }
         }
         team_sync<NT>();
         if (S.anyrot) {
             // Type-2 rotations act on the rows of M in reverse scan order.
-            if (qact) {
+            if (qact && sub == 0) {
                 const int c = qlo + jr;
-                if (sub == 0) {
-                    for (int p = qn.hi - 1; p >= qlo; --p) {
-                        const int part = S.u.m.rpart[p];
-                        if (part < 0) continue;
-                        const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
-                        const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
-                        const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
-                        S.M[rp * LD + c] = cc * mp + ss * mi;
-                        S.M[ri * LD + c] = -ss * mp + cc * mi;
-                    }
+                for (int p = qn.hi - 1; p >= qlo; --p) {
+                    const int part = S.u.m.rpart[p];
+                    if (part < 0) continue;
+                    const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
+                    const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
+                    const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
+                    S.M[rp * LD + c] = cc * mp + ss * mi;
+                    S.M[ri * LD + c] = -ss * mp + cc * mi;
                 }
             }
             team_sync<NT>();
         }
+        BED_PHASE(10 + 8 * d + 4);
 
         // ---- M6: back-multiplication Q_next = blockdiag(Q1, Q2) M (Eq. (4)) --
         {
@@ -694,6 +721,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
             }
         }
         team_sync<NT>();
+        BED_PHASE(10 + 8 * d + 5);
         T* tq = Qc; Qc = Qn; Qn = tq;
         T* tl = Lc; Lc = Ln; Ln = tl;
     }
@@ -723,14 +751,19 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
         for (int k = n - 3; k >= 0; --k) {
             const T tk = S.tau[k];
             if (tk == T(0)) continue;
+            const T* vk = S.Vt + k * NMAX + h * RPC;
             T sacc = T(0);
 #pragma unroll
-            for (int i = 0; i < RPC; ++i) sacc += S.Vt[k * LD + h * RPC + i] * qv[i];
-#pragma unroll
-            for (int o = CPW; o < 64; o <<= 1) sacc += __shfl_xor(sacc, o);
+            for (int i = 0; i < RPC; ++i) sacc += vk[i] * qv[i];
+            if constexpr (CPW <= 1) sacc += xmove<1>(sacc, lane);
+            if constexpr (CPW <= 2) sacc += xmove<2>(sacc, lane);
+            if constexpr (CPW <= 4) sacc += xmove<4>(sacc, lane);
+            if constexpr (CPW <= 8) sacc += xmove<8>(sacc, lane);
+            if constexpr (CPW <= 16) sacc += xmove<16>(sacc, lane);
+            if constexpr (CPW <= 32) sacc += xmove<32>(sacc, lane);
             sacc *= tk;
 #pragma unroll
-            for (int i = 0; i < RPC; ++i) qv[i] -= S.Vt[k * LD + h * RPC + i] * sacc;
+            for (int i = 0; i < RPC; ++i) qv[i] -= vk[i] * sacc;
         }
         // sign canonicalization: largest |.| entry positive, lowest row on ties
         T best = T(-1);
@@ -765,6 +798,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
         }
     }
     team_sync<NT>();
+    BED_PHASE(4);
     for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
         Q_out[e] = S.M[i * LD + j];
         j += NT % n;
@@ -776,6 +810,7 @@ __device__ void syevd_team(const T* __restrict__ Ain, const int n, T* __restrict
     }
     for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
     if (t == 0 && info_out) *info_out = S.capped;
+    BED_PHASE(5);
 }
 
 }  // namespace bed
