@@ -133,6 +133,26 @@ template <int W, typename T> __device__ __forceinline__ T group_prod(T x, int la
     if constexpr (W >= 64) x *= xmove<32>(x, lane);
     return x;
 }
+template <int W> __device__ __forceinline__ int group_min(int x, int lane)
+{
+    if constexpr (W >= 2) x = min(x, xmove<1>(x, lane));
+    if constexpr (W >= 4) x = min(x, xmove<2>(x, lane));
+    if constexpr (W >= 8) x = min(x, xmove<4>(x, lane));
+    if constexpr (W >= 16) x = min(x, xmove<8>(x, lane));
+    if constexpr (W >= 32) x = min(x, xmove<16>(x, lane));
+    if constexpr (W >= 64) x = min(x, xmove<32>(x, lane));
+    return x;
+}
+template <int W> __device__ __forceinline__ int group_max(int x, int lane)
+{
+    if constexpr (W >= 2) x = max(x, xmove<1>(x, lane));
+    if constexpr (W >= 4) x = max(x, xmove<2>(x, lane));
+    if constexpr (W >= 8) x = max(x, xmove<4>(x, lane));
+    if constexpr (W >= 16) x = max(x, xmove<8>(x, lane));
+    if constexpr (W >= 32) x = max(x, xmove<16>(x, lane));
+    if constexpr (W >= 64) x = max(x, xmove<32>(x, lane));
+    return x;
+}
 template <typename T> __device__ __forceinline__ T wave_sum(T x, int lane)
 {
     return group_sum<64>(x, lane);

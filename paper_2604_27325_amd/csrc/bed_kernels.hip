@@ -4,8 +4,17 @@
 
 namespace bed {
 
+// Waves per SIMD that two resident teams of a shape need (four SIMDs per CU);
+// register allocation is capped accordingly.
+template <int NMAX, int NT> struct Occ {
+    static constexpr int teams_per_cu = NMAX >= 64 ? 2 : (NMAX >= 32 ? 4 : 8);
+    static constexpr int v = (teams_per_cu * NT / 64 + 3) / 4;
+    static constexpr int wpe = v < 1 ? 1 : (v > 8 ? 8 : v);
+};
+#define BED_OCC(NMAX, NT) __attribute__((amdgpu_waves_per_eu(Occ<NMAX, NT>::wpe)))
+
 template <typename T, int NMAX, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ lam,
                 T *__restrict__ Q, int32_t *__restrict__ info)
 {
@@ -18,7 +27,7 @@ k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
 }
 
 template <typename T, int NMAX, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_list(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
              int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count,
              int *counter)
@@ -55,7 +64,7 @@ k_syevd_list(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
 }
 
 template <typename T, int NMAX, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_ptrlist(const PtrItem *__restrict__ items, int count)
 {
     __shared__ Smem<T, NMAX, NT> S;

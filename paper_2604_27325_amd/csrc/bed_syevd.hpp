@@ -19,6 +19,7 @@
 #pragma once
 
 #include "bed_device.hpp"
+#include "bed_mfma.hpp"
 
 // Phase markers: no-ops in the library; a profiling build may define
 // BED_PHASE(id) to timestamp the phases of one team.
@@ -63,9 +64,15 @@ struct Smem {
             T rc[NMAX], rs[NMAX];
             int rpart[NMAX];
             int col[NMAX];
+            int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
+            int ckl[NMAX], ckh[NMAX];  // child block of each row of a merged node
             int nk[NMAX];
             T nrho[NMAX], nzz[NMAX], nfro[NMAX];
         } m;
+        struct {  // back-transform: per block of 16 reflectors, Gram matrix and T factor
+            T gram[((NMAX + 13) / 16) * 256];
+            T tf[((NMAX + 13) / 16) * 256];
+        } b;
     } u;
     int bad;
     int capped;
@@ -87,6 +94,8 @@ __device__ __forceinline__ Node node_of(int e, int d, int n)
     nd.s = ((2 * j + 1) * n) >> (d + 1);
     return nd;
 }
+
+__device__ __forceinline__ int node_index(int e, int d, int n) { return (((e + 1) << d) - 1) / n; }
 
 // 2x2 symmetric Schur decomposition by one Givens/Jacobi rotation (Sec. 2.2).
 template <typename T>
@@ -140,40 +149,292 @@ __device__ __forceinline__ T pick(const T* a, int idx)
     }
 }
 
-template <typename T>
-struct SecVal {
-    T f, f1, f2, eb;
-};
-
-// Secular function Eq. (8) with derivatives Eq. (18), (21), in the shifted
-// variable h = lambda - d_o: delta_i = (d_i - d_o) - h.  Pole sums are split
-// across the LPR lanes of a root's group.
-template <typename T, int LPR>
-__device__ __forceinline__ SecVal<T> sec_eval(const T* dk, const T* zk, int k, T rho, T dorg, T h,
-                                              int sub, int lane)
+// Merge phases M2-M5 of one depth with KPL poles (or items) per lane held in
+// registers: secular roots, Loewner zhat, eigenvector norms and output order,
+// merge-matrix assembly (incl. type-2 rotations).  All team threads call it.
+template <typename T, int NMAX, int NT, int KPL>
+__device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n, const int d,
+                                              const int t, T* __restrict__ Ln)
 {
-    T s0 = 0, s1 = 0, s2 = 0, e = 0;
-    for (int i = sub; i < k; i += LPR) {
-        const T del = (dk[i] - dorg) - h;
-        const T rinv = f_rcp(del);
-        const T zi = zk[i];
-        const T t0 = zi * zi * rinv;
-        const T t1 = t0 * rinv;
-        s0 += t0;
-        s1 += t1;
-        s2 += t1 * rinv;
-        e += f_abs(t0);
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int LPR = NT / NMAX;
+    const int lane = t & 63;
+    const T u = fp<T>::u;
+    const T INF = __builtin_inff();
+    (void)lane;
+
+    // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root ---------
+    const int q = t / LPR, sub = t % LPR;
+    const Node qn = node_of(q < n ? q : 0, d, n);
+    const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
+    const int qlo = qn.lo;
+    const int mq = qn.hi - qn.lo;
+    const int kq = qact ? S.u.m.nk[qlo] : 0;
+    const int jr = q - qlo;
+    const T* dk = S.u.m.dk + qlo;
+    const T* zk = S.u.m.zk + qlo;
+    const T rho = qact ? S.u.m.nrho[qlo] : T(0);
+    {
+        const bool live = qact && jr < kq;
+        // this lane's share of the poles: i = sub + LPR*j (absent: +inf, 0)
+        T pv[KPL], z2[KPL], df[KPL];
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int i = sub + LPR * j;
+            const bool ok = live && i < kq;
+            const T dv = dk[ok ? i : 0], zv = zk[ok ? i : 0];
+            pv[j] = ok ? dv : INF;
+            z2[j] = ok ? zv * zv : T(0);
+        }
+        int o = jr, state = 0, nmulti = 0, nhal = 0;
+        bool done = !live, capped = false;
+        T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
+        T dorg = live ? dk[jr] : T(0);
+        if (live) {
+            if (jr < kq - 1) {
+                gap = dk[jr + 1] - dk[jr];
+                h = T(0.5) * gap;  // Eq. (13): midpoint of the root's own bracket
+                w0 = gap;
+                state = 1;
+            } else {
+                top = rho * S.u.m.nzz[qlo];
+                const T ubf = S.u.m.nfro[qlo] - dk[jr];  // Eq. (10)-(11)
+                w0 = top;
+                if (ubf > T(0) && ubf < top) {
+                    h = ubf;
+                    state = 0;
+                } else {
+                    h = T(0.5) * top;
+                    state = 1;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
+        int rounds = 0;
+        // Progressive removal (Eq. (22)): a converged root's lanes idle; the
+        // wave leaves the loop once all of its roots have stopped.
+        while (__ballot(!done)) {
+            ++rounds;
+            if (!done) {
+                // Eq. (8), (18), (21) at h: delta_i = (d_i - d_o) - h
+                T s0 = 0, s1 = 0, s2 = 0, e = 0;
+#pragma unroll
+                for (int j = 0; j < KPL; ++j) {
+                    const T rinv = f_rcp(df[j] - h);
+                    const T t0 = z2[j] * rinv;
+                    const T t1 = t0 * rinv;
+                    s0 += t0;
+                    s1 += t1;
+                    s2 = fma(t1, rinv, s2);
+                    e += f_abs(t0);
+                }
+                s0 = group_sum<LPR>(s0, lane);
+                s1 = group_sum<LPR>(s1, lane);
+                s2 = group_sum<LPR>(s2, lane);
+                e = group_sum<LPR>(e, lane);
+                const T f = T(1) + rho * s0;
+                const T f1 = rho * s1;
+                const T f2 = T(2) * rho * s2;
+                const T eb = T(8) * u * (T(1) + rho * e);
+                if (state == 0) {  // confirm the Frobenius bound
+                    if (f >= T(0)) top = h;
+                    w0 = top;
+                    h = T(0.5) * top;
+                    state = 1;
+                } else if (state == 1 || state == 2) {  // bisection / multi-section
+                    if (f == T(0)) {
+                        done = true;
+                    } else {
+                        if (state == 1) {
+                            if (jr < kq - 1) {
+                                if (f > T(0)) {
+                                    L = T(0);
+                                    U = h;
+                                } else {
+                                    o = jr + 1;  // root nearer d_{j+1}: shift origin
+                                    dorg = dk[jr + 1];
+#pragma unroll
+                                    for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
+                                    L = h - gap;
+                                    U = T(0);
+                                }
+                            } else {
+                                if (f > T(0)) {
+                                    L = T(0);
+                                    U = h;
+                                } else {
+                                    L = h;
+                                    U = top;
+                                }
+                            }
+                        } else {
+                            if (f > T(0)) U = h;
+                            else L = h;
+                            ++nmulti;
+                        }
+                        if (nmulti < 3 && (U - L) > T(1e-2) * w0) {
+                            // Eq. (16): probe toward the origin pole
+                            h = (o == jr) ? L + T(0.25) * (U - L) : U - T(0.25) * (U - L);
+                            state = 2;
+                        } else {
+                            h = T(0.5) * (L + U);
+                            state = 3;
+                        }
+                    }
+                } else {  // Halley, Eq. (20), safeguarded by the bracket
+                    if (f_abs(f) <= eb) {
+                        done = true;
+                    } else {
+                        if (f > T(0)) U = h;
+                        else L = h;
+                        if (U - L <= T(2) * u * (f_abs(L) + f_abs(U))) {
+                            done = true;
+                        } else {
+                            const T den = T(2) * f1 * f1 - f * f2;
+                            T hn = T(0.5) * (L + U);
+                            if (den > T(0) && f_finite(den)) {
+                                const T cand = h - T(2) * f * f1 * f_rcp(den);
+                                if (cand > L && cand < U) hn = cand;
+                            }
+                            if (hn == h) {
+                                done = true;
+                            } else {
+                                h = hn;
+                                if (++nhal >= SEC_CAP) {
+                                    done = true;
+                                    capped = true;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        BED_COUNT(d, rounds);
+        if (live && sub == 0) {
+            S.u.m.rdo[q] = dorg;
+            S.u.m.rtau[q] = h;
+            S.u.m.itv[q] = dorg + h;
+            if (capped) atomicAdd(&S.capped, 1);
+        }
     }
-    s0 = group_sum<LPR>(s0, lane);
-    s1 = group_sum<LPR>(s1, lane);
-    s2 = group_sum<LPR>(s2, lane);
-    e = group_sum<LPR>(e, lane);
-    SecVal<T> v;
-    v.f = T(1) + rho * s0;
-    v.f1 = rho * s1;
-    v.f2 = T(2) * rho * s2;
-    v.eb = T(8) * fp<T>::u * (T(1) + rho * e);
-    return v;
+    team_sync<NT>();
+    BED_PHASE(10 + 8 * d + 1);
+
+    // ---- M3: Loewner zhat (Eq. (25)) as a product of positive ratios ---------
+    if (qact && jr < kq) {
+        const T di = dk[jr];
+        T p = T(1);
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int jj = sub + LPR * j;
+            const bool ok = jj < kq;
+            const int js = ok ? jj : 0;
+            const T del = (di - S.u.m.rdo[qlo + js]) - S.u.m.rtau[qlo + js];  // d_i - lam_j
+            const T fac = (jj == jr) ? (-del / rho) : (-del / (dk[js] - di));
+            p *= ok ? fac : T(1);
+        }
+        p = group_prod<LPR>(p, lane);
+        if (sub == 0) S.u.m.zh[q] = f_copysign(f_sqrt(p), zk[jr]);
+    }
+    team_sync<NT>();
+    BED_PHASE(10 + 8 * d + 2);
+
+    // ---- M4: eigenvector norms (Eq. (24)) and output order -------------------
+    if (qact && jr < kq) {
+        const T dorg = S.u.m.rdo[q];
+        const T tj = S.u.m.rtau[q];
+        T s2 = T(0);
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int ii = sub + LPR * j;
+            const bool ok = ii < kq;
+            const int is = ok ? ii : 0;
+            const T w = S.u.m.zh[qlo + is] * f_rcp((dk[is] - dorg) - tj);
+            s2 += ok ? w * w : T(0);
+        }
+        s2 = group_sum<LPR>(s2, lane);
+        if (sub == 0) S.u.m.rnrm[q] = f_rcp(f_sqrt(s2));
+    }
+    // rank of item jr among the node's m items (roots, then deflated)
+    if (qact) {
+        const T my = S.u.m.itv[q];
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < KPL; ++j) {
+            const int vv = sub + LPR * j;
+            const bool ok = vv < mq;
+            const T ov = S.u.m.itv[qlo + (ok ? vv : 0)];
+            cnt += (ok && (ov < my || (ov == my && vv < jr))) ? 1 : 0;
+        }
+        cnt = group_sum<LPR>(cnt, lane);
+        if (sub == 0) {
+            S.u.m.col[q] = qlo + cnt;
+            Ln[qlo + cnt] = my;
+        }
+    }
+    team_sync<NT>();
+    BED_PHASE(10 + 8 * d + 3);
+
+    // ---- M5: merge matrix M = P G (U (+) I), rows in child order -------------
+    if (qact) {
+        const int c = S.u.m.col[q];
+        if (jr < kq) {
+            const T dorg = S.u.m.rdo[q];
+            const T tj = S.u.m.rtau[q];
+            const T nr = S.u.m.rnrm[q];
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int ii = sub + LPR * j;
+                if (ii < kq) {
+                    const T del = (dk[ii] - dorg) - tj;  // d_i - lam_j
+                    S.M[S.u.m.ndrow[qlo + ii] * LD + c] = -S.u.m.zh[qlo + ii] * nr * f_rcp(del);
+                } else if (ii < mq) {
+                    S.M[S.u.m.itrow[qlo + ii] * LD + c] = T(0);
+                }
+            }
+        } else {
+            const int myrow = S.u.m.itrow[q];
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int row = qlo + sub + LPR * j;
+                if (row < qlo + mq) S.M[row * LD + c] = (row == myrow) ? T(1) : T(0);
+            }
+        }
+    }
+    team_sync<NT>();
+    if (S.anyrot) {
+        // Type-2 rotations act on the rows of M in reverse scan order.
+        if (qact && sub == 0) {
+            const int c = qlo + jr;
+            for (int p = qn.hi - 1; p >= qlo; --p) {
+                const int part = S.u.m.rpart[p];
+                if (part < 0) continue;
+                const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
+                const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
+                const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
+                S.M[rp * LD + c] = cc * mp + ss * mi;
+                S.M[ri * LD + c] = -ss * mp + cc * mi;
+            }
+        }
+        team_sync<NT>();
+    }
+}
+
+// Calls roots_vectors with the smallest power-of-two KPL >= need.
+template <typename T, int NMAX, int NT, int KPL>
+__device__ __forceinline__ void roots_vectors_dispatch(Smem<T, NMAX, NT>& S, const int n,
+                                                       const int d, const int t, T* Ln, int need)
+{
+    if constexpr (KPL >= NMAX / (NT / NMAX)) {
+        roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln);
+    } else {
+        if (need <= KPL)
+            roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln);
+        else
+            roots_vectors_dispatch<T, NMAX, NT, KPL * 2>(S, n, d, t, Ln, need);
+    }
 }
 
 template <typename T, int NMAX, int NT>
@@ -307,6 +568,11 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         }
     }
     team_sync<NT>();
+    // The staging buffer becomes the merge matrix M: clear it so that entries
+    // outside every node block (never written by a merge) are zero -- the MFMA
+    // back-multiplication reads them against zero A entries.
+    for (int e = t; e < NMAX * LD; e += NT) S.M[e] = T(0);
+    team_sync<NT>();
     BED_PHASE(2);
 
     // ------------------------------------------------------------ tear + leaves
@@ -366,6 +632,12 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T bet = act ? S.b[s - 1] : T(0);
             const T rho = f_abs(bet);
             const T sgm = (bet < T(0)) ? T(-1) : T(1);
+            if (e < NMAX) {
+                S.u.m.nlo[e] = (e < n) ? nd.lo : e;
+                S.u.m.nhi[e] = (e < n) ? nd.hi : e;
+                S.u.m.ckl[e] = act ? (e < s ? lo : s) : NMAX;
+                S.u.m.ckh[e] = act ? (e < s ? s : hi) : 0;
+            }
             if (act) {
                 const T de = Lc[e];
                 const T ze = (e < s) ? sgm * Qc[(s - 1) * LD + e] : Qc[s * LD + e];
@@ -479,245 +751,60 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         team_sync<NT>();
         BED_PHASE(10 + 8 * d + 0);
 
-        // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root -----
-        const int q = t / LPR, sub = t % LPR;
-        const Node qn = node_of(q < n ? q : 0, d, n);
-        const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
-        const int qlo = qn.lo;
-        const int kq = qact ? S.u.m.nk[qlo] : 0;
-        const int jr = q - qlo;
-        const T* dk = S.u.m.dk + qlo;
-        const T* zk = S.u.m.zk + qlo;
-        const T rho = qact ? S.u.m.nrho[qlo] : T(0);
         {
-            const bool live = qact && jr < kq;
-            int o = jr, state = 0, nmulti = 0, nhal = 0;
-            bool done = !live, capped = false;
-            T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
-            T dorg = live ? dk[jr] : T(0);
-            if (live) {
-                if (jr < kq - 1) {
-                    gap = dk[jr + 1] - dk[jr];
-                    h = T(0.5) * gap;  // Eq. (13): midpoint of the root's own bracket
-                    w0 = gap;
-                    state = 1;
-                } else {
-                    top = rho * S.u.m.nzz[qlo];
-                    const T ubf = S.u.m.nfro[qlo] - dk[jr];  // Eq. (10)-(11)
-                    w0 = top;
-                    if (ubf > T(0) && ubf < top) {
-                        h = ubf;
-                        state = 0;
-                    } else {
-                        h = T(0.5) * top;
-                        state = 1;
-                    }
-                }
-            }
-            // Progressive removal (Eq. (22)): a converged root's lanes idle; the
-            // wave leaves the loop once all of its roots have stopped.
-            int rounds = 0;
-            while (__ballot(!done)) {
-                ++rounds;
-                if (!done) {
-                    const SecVal<T> v = sec_eval<T, LPR>(dk, zk, kq, rho, dorg, h, sub, lane);
-                    if (state == 0) {  // confirm the Frobenius bound
-                        if (v.f >= T(0)) top = h;
-                        w0 = top;
-                        h = T(0.5) * top;
-                        state = 1;
-                    } else if (state == 1 || state == 2) {  // bisection / multi-section
-                        if (v.f == T(0)) {
-                            done = true;
-                        } else {
-                            if (state == 1) {
-                                if (jr < kq - 1) {
-                                    if (v.f > T(0)) {
-                                        L = T(0);
-                                        U = h;
-                                    } else {
-                                        o = jr + 1;  // root nearer d_{j+1}: shift origin
-                                        dorg = dk[jr + 1];
-                                        L = h - gap;
-                                        U = T(0);
-                                    }
-                                } else {
-                                    if (v.f > T(0)) {
-                                        L = T(0);
-                                        U = h;
-                                    } else {
-                                        L = h;
-                                        U = top;
-                                    }
-                                }
-                            } else {
-                                if (v.f > T(0)) U = h;
-                                else L = h;
-                                ++nmulti;
-                            }
-                            if (nmulti < 3 && (U - L) > T(1e-2) * w0) {
-                                // Eq. (16): probe toward the origin pole
-                                h = (o == jr) ? L + T(0.25) * (U - L) : U - T(0.25) * (U - L);
-                                state = 2;
-                            } else {
-                                h = T(0.5) * (L + U);
-                                state = 3;
-                            }
-                        }
-                    } else {  // Halley, Eq. (20), safeguarded by the bracket
-                        if (f_abs(v.f) <= v.eb) {
-                            done = true;
-                        } else {
-                            if (v.f > T(0)) U = h;
-                            else L = h;
-                            if (U - L <= T(2) * u * (f_abs(L) + f_abs(U))) {
-                                done = true;
-                            } else {
-                                const T den = T(2) * v.f1 * v.f1 - v.f * v.f2;
-                                T hn = T(0.5) * (L + U);
-                                if (den > T(0) && f_finite(den)) {
-                                    const T cand = h - T(2) * v.f * v.f1 * f_rcp(den);
-                                    if (cand > L && cand < U) hn = cand;
-                                }
-                                if (hn == h) {
-                                    done = true;
-                                } else {
-                                    h = hn;
-                                    if (++nhal >= SEC_CAP) {
-                                        done = true;
-                                        capped = true;
-                                    }
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-            BED_COUNT(d, rounds);
-            if (live && sub == 0) {
-                S.u.m.rdo[q] = dorg;
-                S.u.m.rtau[q] = h;
-                S.u.m.itv[q] = dorg + h;
-                if (capped) atomicAdd(&S.capped, 1);
-            }
-        }
-        team_sync<NT>();
-        BED_PHASE(10 + 8 * d + 1);
-
-        // ---- M3: Loewner zhat (Eq. (25)) as a product of positive ratios -----
-        if (qact && jr < kq) {
-            const T di = dk[jr];
-            T p = T(1);
-            for (int jj = sub; jj < kq; jj += LPR) {
-                const T del = (di - S.u.m.rdo[qlo + jj]) - S.u.m.rtau[qlo + jj];  // d_i - lam_j
-                p *= (jj == jr) ? (-del / rho) : (-del / (dk[jj] - di));
-            }
-            p = group_prod<LPR>(p, lane);
-            if (sub == 0) S.u.m.zh[q] = f_copysign(f_sqrt(p), zk[jr]);
-        }
-        team_sync<NT>();
-        BED_PHASE(10 + 8 * d + 2);
-
-        // ---- M4: eigenvector norms (Eq. (24)) and output order ---------------
-        {
-            const int mq = qn.hi - qn.lo;
-            if (qact && jr < kq) {
-                const T dorg = S.u.m.rdo[q];
-                const T tj = S.u.m.rtau[q];
-                T s2 = T(0);
-                for (int ii = sub; ii < kq; ii += LPR) {
-                    const T w = S.u.m.zh[qlo + ii] * f_rcp((dk[ii] - dorg) - tj);
-                    s2 += w * w;
-                }
-                s2 = group_sum<LPR>(s2, lane);
-                if (sub == 0) S.u.m.rnrm[q] = f_rcp(f_sqrt(s2));
-            }
-            // rank of item jr among the node's m items (roots, then deflated)
-            if (qact) {
-                const T my = S.u.m.itv[q];
-                int cnt = 0;
-                for (int vv = sub; vv < mq; vv += LPR) {
-                    const T ov = S.u.m.itv[qlo + vv];
-                    cnt += (ov < my || (ov == my && vv < jr)) ? 1 : 0;
-                }
-                cnt = group_sum<LPR>(cnt, lane);
-                if (sub == 0) {
-                    S.u.m.col[q] = qlo + cnt;
-                    Ln[qlo + cnt] = my;
-                }
-            }
-        }
-        team_sync<NT>();
-        BED_PHASE(10 + 8 * d + 3);
-
-        // ---- M5: merge matrix M = P G (U (+) I), rows in child order ---------
-        if (qact) {
-            const int mq = qn.hi - qn.lo;
-            const int c = S.u.m.col[q];
-            if (jr < kq) {
-                const T dorg = S.u.m.rdo[q];
-                const T tj = S.u.m.rtau[q];
-                const T nr = S.u.m.rnrm[q];
-                for (int ii = sub; ii < kq; ii += LPR) {
-                    const T del = (dk[ii] - dorg) - tj;  // d_i - lam_j
-                    S.M[S.u.m.ndrow[qlo + ii] * LD + c] = -S.u.m.zh[qlo + ii] * nr * f_rcp(del);
-                }
-                for (int ii = kq + sub; ii < mq; ii += LPR)
-                    S.M[S.u.m.itrow[qlo + ii] * LD + c] = T(0);
-            } else {
-                const int myrow = S.u.m.itrow[q];
-                for (int row = qlo + sub; row < qlo + mq; row += LPR)
-                    S.M[row * LD + c] = (row == myrow) ? T(1) : T(0);
-            }
-        }
-        team_sync<NT>();
-        if (S.anyrot) {
-            // Type-2 rotations act on the rows of M in reverse scan order.
-            if (qact && sub == 0) {
-                const int c = qlo + jr;
-                for (int p = qn.hi - 1; p >= qlo; --p) {
-                    const int part = S.u.m.rpart[p];
-                    if (part < 0) continue;
-                    const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
-                    const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
-                    const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
-                    S.M[rp * LD + c] = cc * mp + ss * mi;
-                    S.M[ri * LD + c] = -ss * mp + cc * mi;
-                }
-            }
-            team_sync<NT>();
+            // poles (and items) per lane at this depth: ceil(max node size / LPR)
+            const int need = ((((n + (1 << d) - 1) >> d)) + LPR - 1) / LPR;
+            roots_vectors_dispatch<T, NMAX, NT, 1>(S, n, d, t, Ln, need);
         }
         BED_PHASE(10 + 8 * d + 4);
 
         // ---- M6: back-multiplication Q_next = blockdiag(Q1, Q2) M (Eq. (4)) --
+        // 16x16 MFMA tiles over the block-diagonal band; A = Q_cur restricted
+        // to each row's child block, B = M (zero outside the node blocks).
         {
-            const Node rn = node_of(r < n ? r : 0, d, n);
-            const bool ract = r < n;
-            const bool merged = ract && (rn.hi - rn.lo >= 3);
-            if (merged) {
-                const int klo = (r < rn.s) ? rn.lo : rn.s;
-                const int khi = (r < rn.s) ? rn.s : rn.hi;
-                T acc[CPT];
+            using MF = Mf<T>;
+            constexpr int RT = NMAX / 16;
+            const int i16 = lane & 15;
+            for (int tile = wave; tile < RT * RT; tile += NW) {
+                const int r0 = 16 * (tile / RT), c0 = 16 * (tile % RT);
+                if (r0 >= n || c0 >= n) continue;
+                const int r = r0 + i16, c = c0 + i16;
+                const int ckl = S.u.m.ckl[r], ckh = S.u.m.ckh[r];
+                const int rlo = S.u.m.nlo[r < n ? r : r0], clo = S.u.m.nlo[c < n ? c : c0];
+                const int klo = group_min<16>(ckl, lane), khi = group_max<16>(ckh, lane);
+                const int rmin = group_min<16>(rlo, lane), rmax = group_max<16>(rlo, lane);
+                const int cmin = group_min<16>(clo, lane), cmax = group_max<16>(clo, lane);
+                if (klo >= khi || max(rmin, cmin) > min(rmax, cmax)) continue;
+                typename MF::acc acc = MF::zero();
+                // K in chunks of four MFMA steps; operands of a chunk are
+                // loaded before its MFMAs are issued
+                for (int kb = klo & ~3; kb < khi; kb += 16) {
+                    T av[4], bv[4];
 #pragma unroll
-                for (int j = 0; j < CPT; ++j) acc[j] = T(0);
-                for (int kk = klo; kk < khi; ++kk) {
-                    const T av = Qc[r * LD + kk];
+                    for (int j = 0; j < 4; ++j) {
+                        const int kc = kb + 4 * j;
+                        const int k = (kc < khi) ? kc + (lane >> 4) : 0;
+                        av[j] = (k >= ckl && k < ckh) ? Qc[r * LD + k] : T(0);
+                        bv[j] = S.M[k * LD + c];
+                    }
 #pragma unroll
-                    for (int j = 0; j < CPT; ++j) acc[j] += av * S.M[kk * LD + g * CPT + j];
+                    for (int j = 0; j < 4; ++j)
+                        if (kb + 4 * j < khi) acc = MF::mma(av[j], bv[j], acc);
                 }
 #pragma unroll
-                for (int j = 0; j < CPT; ++j) {
-                    const int c = g * CPT + j;
-                    if (c >= rn.lo && c < rn.hi) Qn[r * LD + c] = acc[j];
+                for (int v = 0; v < 4; ++v) {
+                    const int row = r0 + MF::crow(lane, v);
+                    const int lo = S.u.m.nlo[row], hi = S.u.m.nhi[row];
+                    if (row < n && c < n && hi - lo >= 3 && lo == clo) Qn[row * LD + c] = acc[v];
                 }
-            } else if (ract) {
-                // nodes not merged at this depth keep their block
-#pragma unroll
-                for (int j = 0; j < CPT; ++j) {
-                    const int c = g * CPT + j;
-                    if (c >= rn.lo && c < rn.hi) Qn[r * LD + c] = Qc[r * LD + c];
+            }
+            // nodes not merged at this depth keep their block
+            for (int e = t; e < n; e += NT) {
+                const int lo = S.u.m.nlo[e], hi = S.u.m.nhi[e];
+                if (hi - lo < 3) {
+                    for (int cc = lo; cc < hi; ++cc) Qn[e * LD + cc] = Qc[e * LD + cc];
+                    Ln[e] = Lc[e];
                 }
-                if (g == 0) Ln[r] = Lc[r];
             }
         }
         team_sync<NT>();
@@ -733,74 +820,150 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     }
 
     // ------------------------------------------------------------ back-transform
-    // Q_A = H_0 H_1 ... H_{n-3} Q_T.  Wave w owns columns [w*CPW, (w+1)*CPW);
-    // lane l holds rows [h*RPC, (h+1)*RPC) of column w*CPW + l % CPW.
+    // Q_A = H_0 H_1 ... H_{n-3} Q_T in compact-WY blocks of 16 reflectors,
+    // H_{16b} ... H_{16b+15} = I - V_b T_b V_b^T (T_b upper triangular), applied
+    // for b = last .. 0.  Each wave keeps whole 16-column tiles of Q in MFMA
+    // accumulators for all blocks, so the update needs no team barrier.
     {
-        constexpr int CPW = NMAX / NW;
-        constexpr int CH = 64 / CPW;
-        constexpr int RPC = NMAX / CH;
-        static_assert(CPW * NW == NMAX && CH * CPW == 64 && RPC * CH == NMAX, "bt geometry");
-        const int c = wave * CPW + (lane % CPW);
-        const int h = lane / CPW;
-        T qv[RPC];
+        using MF = Mf<T>;
+        constexpr int RT = NMAX / 16;
+        const int nb = n > 2 ? n - 2 : 0;  // reflectors
+        const int NB = (nb + 15) / 16;
+        const int i16 = lane & 15;
+        // Gram matrices G_b = V_b^T V_b (one wave per block)
+        for (int bk = wave; bk < NB; bk += NW) {
+            const int k0 = 16 * bk;
+            typename MF::acc g = MF::zero();
+            const bool okr = k0 + i16 < nb;
+            for (int rt = bk; rt < RT; ++rt) {
 #pragma unroll
-        for (int i = 0; i < RPC; ++i) {
-            const int row = h * RPC + i;
-            qv[i] = (row < n && c < n) ? Qc[row * LD + c] : T(0);
-        }
-        for (int k = n - 3; k >= 0; --k) {
-            const T tk = S.tau[k];
-            if (tk == T(0)) continue;
-            const T* vk = S.Vt + k * NMAX + h * RPC;
-            T sacc = T(0);
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int row = 16 * rt + MF::crow(lane, s4);
+                    const T vv = okr ? S.Vt[(k0 + i16) * NMAX + row] : T(0);
+                    g = MF::mma(vv, vv, g);
+                }
+            }
 #pragma unroll
-            for (int i = 0; i < RPC; ++i) sacc += vk[i] * qv[i];
-            if constexpr (CPW <= 1) sacc += xmove<1>(sacc, lane);
-            if constexpr (CPW <= 2) sacc += xmove<2>(sacc, lane);
-            if constexpr (CPW <= 4) sacc += xmove<4>(sacc, lane);
-            if constexpr (CPW <= 8) sacc += xmove<8>(sacc, lane);
-            if constexpr (CPW <= 16) sacc += xmove<16>(sacc, lane);
-            if constexpr (CPW <= 32) sacc += xmove<32>(sacc, lane);
-            sacc *= tk;
+            for (int v = 0; v < 4; ++v) S.u.b.gram[bk * 256 + MF::crow(lane, v) * 16 + i16] = g[v];
+            wave_sync();
+            // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j)
+            if (lane < 16) {
+                T trow[16];
 #pragma unroll
-            for (int i = 0; i < RPC; ++i) qv[i] -= vk[i] * sacc;
-        }
-        // sign canonicalization: largest |.| entry positive, lowest row on ties
-        T best = T(-1);
-        int brow = 1 << 20;
-        T bval = T(0);
+                for (int j = 0; j < 16; ++j) {
+                    const T tj = (k0 + j < nb) ? S.tau[k0 + j] : T(0);
+                    T acc = T(0);
 #pragma unroll
-        for (int i = 0; i < RPC; ++i) {
-            const int row = h * RPC + i;
-            const T av = f_abs(qv[i]);
-            if (row < n && (av > best)) {
-                best = av;
-                brow = row;
-                bval = qv[i];
+                    for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], S.u.b.gram[bk * 256 + kk * 16 + j], acc);
+                    trow[j] = (lane < j) ? -tj * acc : (lane == j ? tj : T(0));
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) S.u.b.tf[bk * 256 + lane * 16 + j] = trow[j];
             }
         }
+        team_sync<NT>();
+        for (int ct = wave; ct < RT; ct += NW) {
+            const int c0 = 16 * ct;
+            if (c0 >= n) continue;
+            const int c = c0 + i16;
+            typename MF::acc q[RT];
 #pragma unroll
-        for (int o = CPW; o < 64; o <<= 1) {
-            const T ob = __shfl_xor(best, o);
-            const int orow = __shfl_xor(brow, o);
-            const T oval = __shfl_xor(bval, o);
-            if (ob > best || (ob == best && orow < brow)) {
-                best = ob;
-                brow = orow;
-                bval = oval;
+            for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rt + MF::crow(lane, v);
+                    q[rt][v] = (row < n && c < n) ? Qc[row * LD + c] : T(0);
+                }
             }
-        }
-        const T sgn = (bval < T(0)) ? T(-1) : T(1);
+            for (int bk = NB - 1; bk >= 0; --bk) {
+                const int k0 = 16 * bk;
+                const bool okr = k0 + i16 < nb;
+                // operands of this block, loaded before the MFMA chain
+                T va[RT][4], vb[RT][4], tv[4];
 #pragma unroll
-        for (int i = 0; i < RPC; ++i) {
-            const int row = h * RPC + i;
-            if (row < n && c < n) S.M[row * LD + c] = sgn * qv[i];
+                for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int row = 16 * rt + MF::crow(lane, s4);
+                        const int kr = k0 + MF::crow(lane, s4);
+                        va[rt][s4] = okr ? S.Vt[(k0 + i16) * NMAX + row] : T(0);
+                        vb[rt][s4] = (kr < nb) ? -S.Vt[kr * NMAX + 16 * rt + i16] : T(0);
+                    }
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) tv[s4] = S.u.b.tf[bk * 256 + i16 * 16 + MF::crow(lane, s4)];
+                // X = V_b^T Q (16 x 16 tile of this column block); rows of V_b
+                // above k0 + 1 are zero, so row tiles below bk are skipped
+                typename MF::acc x = MF::zero();
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < bk) continue;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) x = MF::mma(va[rt][s4], q[rt][s4], x);
+                }
+                // Y = T_b X
+                typename MF::acc y = MF::zero();
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) y = MF::mma(tv[s4], x[s4], y);
+                // Q -= V_b Y
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (rt < bk) continue;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) q[rt] = MF::mma(vb[rt][s4], y[s4], q[rt]);
+                }
+            }
+            // sign canonicalization: largest |.| entry positive, lowest row on ties
+            T best = T(-1), bval = T(0);
+            int brow = 1 << 20;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rt + MF::crow(lane, v);
+                    const T av = f_abs(q[rt][v]);
+                    if (row < n && (av > best || (av == best && row < brow))) {
+                        best = av;
+                        brow = row;
+                        bval = q[rt][v];
+                    }
+                }
+            }
+            {
+                const T ob = xmove<16>(best, lane);
+                const int orow = xmove<16>(brow, lane);
+                const T oval = xmove<16>(bval, lane);
+                if (ob > best || (ob == best && orow < brow)) {
+                    best = ob;
+                    brow = orow;
+                    bval = oval;
+                }
+            }
+            {
+                const T ob = xmove<32>(best, lane);
+                const int orow = xmove<32>(brow, lane);
+                const T oval = xmove<32>(bval, lane);
+                if (ob > best || (ob == best && orow < brow)) {
+                    best = ob;
+                    brow = orow;
+                    bval = oval;
+                }
+            }
+            const T sgn = (bval < T(0)) ? T(-1) : T(1);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rt + MF::crow(lane, v);
+                    if (row < n && c < n) Qn[row * LD + c] = sgn * q[rt][v];
+                }
+            }
         }
     }
     team_sync<NT>();
     BED_PHASE(4);
     for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
-        Q_out[e] = S.M[i * LD + j];
+        Q_out[e] = Qn[i * LD + j];
         j += NT % n;
         i += NT / n;
         if (j >= n) {
