@@ -92,12 +92,14 @@ bed_status bed_syevals(bed_dtype dt, int64_t batch, const int32_t *n, const void
 
 /* Plans: descriptors (offsets, size classes, work order) and the schedule
  * are built once; bed_plan_run enqueues one launch per size class (or one
- * persistent launch) and allocates nothing, so it may be captured into a HIP
- * graph.  tune == NULL takes the autotuner's choice for this size mix.
- * bed_plan_create during stream capture of the current thread's stream
- * returns BED_ERR_CAPTURE. */
+ * persistent launch per class) and allocates nothing, so it may be captured
+ * into a HIP graph.  tune == NULL takes the autotuner's choice for this size
+ * mix (else the default schedule).  bed_plan_create allocates and copies the
+ * descriptors synchronously; `stream` is the stream the plan will run on and
+ * is only inspected: while it is being captured, BED_ERR_CAPTURE is returned
+ * and nothing is allocated. */
 bed_status bed_plan_create(bed_plan **plan, bed_dtype dt, int64_t batch, const int32_t *n,
-                           const bed_tune *tune);
+                           const bed_tune *tune, void *stream);
 bed_status bed_plan_run(const bed_plan *plan, const void *A, void *lambda, void *Q,
                         int32_t *info, void *stream);
 bed_status bed_plan_get_tune(const bed_plan *plan, bed_tune *out);

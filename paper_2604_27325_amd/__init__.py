@@ -64,7 +64,7 @@ def load_library():
     lib.bed_syevd.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, vp]
     lib.bed_syevals.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp]
     lib.bed_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, i32p,
-                                    ctypes.POINTER(Tune)]
+                                    ctypes.POINTER(Tune), vp]
     lib.bed_plan_run.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.bed_plan_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
     lib.bed_plan_destroy.argtypes = [vp]
@@ -239,7 +239,7 @@ class Plan:
     """A reusable schedule for one (dtype, n[]) batch; run() allocates nothing
     and can be captured in a HIP graph."""
 
-    def __init__(self, dtype, n_list, tune=None):
+    def __init__(self, dtype, n_list, tune=None, stream=None):
         lib = load_library()
         self._n_arr, n_ptr = _n_array(n_list)
         self.dtype = dtype
@@ -249,7 +249,8 @@ class Plan:
             t = Tune(**{k: int(tune.get(k, 0)) for k, _ in Tune._fields_}) \
                 if isinstance(tune, dict) else tune
         _check(lib.bed_plan_create(ctypes.byref(h), _dtype_code(dtype), len(self._n_arr), n_ptr,
-                                   ctypes.byref(t) if t is not None else None))
+                                   ctypes.byref(t) if t is not None else None,
+                                   _stream_ptr(stream)))
         self._h = h
 
     def tune(self):

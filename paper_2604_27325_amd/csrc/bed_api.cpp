@@ -186,14 +186,14 @@ static bed_status plan_build(bed_plan *p, bed_dtype dt, int64_t batch, const int
 }
 
 extern "C" bed_status bed_plan_create(bed_plan **plan, bed_dtype dt, int64_t batch,
-                                      const int32_t *n, const bed_tune *tune)
+                                      const int32_t *n, const bed_tune *tune, void *stream)
 {
     if (!plan) return fail(BED_ERR_INVALID_ARG, "plan is NULL");
     *plan = nullptr;
     bed_status st = check_sizes(dt, batch, n);
     if (st != BED_OK) return st;
-    if (stream_capturing(nullptr))
-        return fail(BED_ERR_CAPTURE, "bed_plan_create during stream capture");
+    if (stream_capturing((hipStream_t)stream))
+        return fail(BED_ERR_CAPTURE, "bed_plan_create while its stream is being captured");
     bed_tune t = tune ? *tune : tuned_or_default(dt, batch, n);
     if (t.threads_big == 0) t.threads_big = 256;
     if (t.threads_mid == 0) t.threads_mid = 64;
@@ -308,7 +308,7 @@ static bed_status solve(bed_dtype dt, int64_t batch, const int32_t *n, const voi
         } else {
             if (stream_capturing(s))
                 return fail(BED_ERR_CAPTURE, "first bed_syevd for a new size mix during capture");
-            st = bed_plan_create(&p, dt, batch, n, nullptr);
+            st = bed_plan_create(&p, dt, batch, n, nullptr, stream);
             if (st != BED_OK) return st;
             g_cache.emplace(std::move(key), p);
         }

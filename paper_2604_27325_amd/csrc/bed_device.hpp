@@ -34,13 +34,18 @@ template <typename T> __device__ __forceinline__ T f_nan();
 template <> __device__ __forceinline__ float f_nan<float>() { return __builtin_nanf(""); }
 template <> __device__ __forceinline__ double f_nan<double>() { return __builtin_nan(""); }
 
-// binary32: the hardware reciprocal / square root (about 1 ulp); binary64:
-// IEEE division and square root.
-__device__ __forceinline__ float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// binary32: the hardware reciprocal (about 1 ulp) refined by one Newton step
+// r' = r + r (1 - x r), and the hardware square root; binary64: IEEE division
+// and square root.
+__device__ __forceinline__ float f_rcp(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 __device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float f_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ float f_div(float a, float b) { return a * f_rcp(b); }
 __device__ __forceinline__ double f_div(double a, double b) { return a / b; }
 
 // Orders LDS traffic between the lanes of one wave: a wave executes its LDS

@@ -160,7 +160,9 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     constexpr int LPR = NT / NMAX;
     const int lane = t & 63;
     const T u = fp<T>::u;
-    const T INF = __builtin_inff();
+    // absent poles: a far, finite pole with zero weight (its terms vanish and
+    // its reciprocal stays a normal number)
+    const T FAR = sizeof(T) == 4 ? T(1e30f) : T(1e300);
     (void)lane;
 
     // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root ---------
@@ -176,14 +178,14 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     const T rho = qact ? S.u.m.nrho[qlo] : T(0);
     {
         const bool live = qact && jr < kq;
-        // this lane's share of the poles: i = sub + LPR*j (absent: +inf, 0)
+        // this lane's share of the poles: i = sub + LPR*j
         T pv[KPL], z2[KPL], df[KPL];
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
             const int i = sub + LPR * j;
             const bool ok = live && i < kq;
             const T dv = dk[ok ? i : 0], zv = zk[ok ? i : 0];
-            pv[j] = ok ? dv : INF;
+            pv[j] = ok ? dv : FAR;
             z2[j] = ok ? zv * zv : T(0);
         }
         int o = jr, state = 0, nmulti = 0, nhal = 0;
@@ -514,7 +516,9 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 const T mu = f_sqrt(x0 * x0 + sig);
                 alpha = (x0 < T(0)) ? mu : -mu;
                 rv0 = f_rcp(x0 - alpha);
-                tauk = f_div(alpha - x0, alpha);
+                // tau = 2 / (v^T v) of the v actually formed (v_0 = 1, v_i = x_i rv0),
+                // so each reflector is orthogonal to rounding whatever rv0's error
+                tauk = T(2) / (T(1) + sig * rv0 * rv0);
             }
             const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr * rv0 : T(0));
             if (t == 0) {

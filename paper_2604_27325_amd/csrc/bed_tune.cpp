@@ -132,7 +132,7 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
     bed_tune best = default_tune();
     for (const bed_tune &t : cands) {
         bed_plan *p = nullptr;
-        if (bed_plan_create(&p, dt, batch, n, &t) != BED_OK) continue;
+        if (bed_plan_create(&p, dt, batch, n, &t, stream) != BED_OK) continue;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w) ok = plan_run_impl(p, A, lambda, Q, nullptr, s) == BED_OK;
         const int reps = 5;

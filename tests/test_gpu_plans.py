@@ -1,0 +1,123 @@
+"""Uneven batching: plans (static and persistent work lists), HIP-graph replay
+and the autotuner, all against the oracle and against each other."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27325_amd import workloads
+from tests.parity import compare_batch
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2604_27325_amd as bed  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def uneven():
+    ns, mats = workloads.uneven(batch=1024)
+    _, flat = workloads.pack(mats)
+    return ns, mats, flat
+
+
+def run_plan(plan, ns, flat_t):
+    lam = torch.empty(int(np.sum(ns)), device=DEV)
+    Q = torch.empty_like(flat_t)
+    info = torch.empty(len(ns), dtype=torch.int32, device=DEV)
+    plan.run(flat_t, lam, Q, info)
+    torch.cuda.synchronize()
+    return lam, Q, info
+
+
+def split(ns, lam, Q):
+    out_l, out_q, oA, oL = [], [], 0, 0
+    for n in ns:
+        out_l.append(lam[oL:oL + n])
+        out_q.append(Q[oA:oA + n * n].reshape(n, n))
+        oA += n * n
+        oL += n
+    return out_l, out_q
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_plan_matches_oracle(uneven, persistent):
+    ns, mats, flat = uneven
+    plan = bed.Plan(torch.float32, ns, tune={"persistent": persistent})
+    lam, Q, info = run_plan(plan, ns, torch.from_numpy(flat).to(DEV))
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    lg, qg = split(ns, lam.cpu().numpy(), Q.cpu().numpy())
+    lo, qo = split(ns, lam_o, Q_o)
+    worst, fails = compare_batch(mats, lg, qg, lo, qo, np.float32, info=info.cpu().numpy())
+    print(f"[plan persistent={persistent}] worst {worst}", flush=True)
+    assert not fails, fails[:3]
+
+
+def test_schedules_are_bitwise_identical(uneven):
+    """The per-matrix kernel depends only on (n, dtype): static, persistent and
+    the convenience path give the same bits, and repeated persistent launches
+    (self-resetting work counter) too."""
+    ns, mats, flat = uneven
+    A = torch.from_numpy(flat).to(DEV)
+    outs = []
+    for tune in ({"persistent": 0}, {"persistent": 1}, {"persistent": 1, "order": 1}):
+        plan = bed.Plan(torch.float32, ns, tune=tune)
+        for _ in range(2):
+            outs.append(run_plan(plan, ns, A))
+    lam_c, Q_c, _ = bed.syevd_packed(ns, A)
+    for lam, Q, info in outs:
+        assert torch.equal(lam, lam_c) and torch.equal(Q, Q_c)
+
+
+def test_hip_graph_replay(uneven):
+    ns, mats, flat = uneven
+    A = torch.from_numpy(flat).to(DEV)
+    plan = bed.Plan(torch.float32, ns, tune={"persistent": 1})
+    lam = torch.empty(int(np.sum(ns)), device=DEV)
+    Q = torch.empty_like(A)
+    info = torch.zeros(len(ns), dtype=torch.int32, device=DEV)
+    ref_l, ref_q, _ = run_plan(plan, ns, A)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(A, lam, Q, info)  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.run(A, lam, Q, info)
+    for rep in range(4):
+        lam.fill_(-1.0)
+        Q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (A * 2.0).sum().item()  # eager work between replays
+        assert torch.equal(lam, ref_l) and torch.equal(Q, ref_q), f"replay {rep}"
+
+
+def test_autotune_returns_valid_schedule(uneven):
+    ns, mats, flat = uneven
+    A = torch.from_numpy(flat).to(DEV)
+    lam = torch.empty(int(np.sum(ns)), device=DEV)
+    Q = torch.empty_like(A)
+    t = bed.autotune(torch.float32, ns, A, lam, Q)
+    assert t["threads_big"] in (128, 256, 512) and t["threads_mid"] in (64, 128)
+    plan = bed.Plan(torch.float32, ns, tune=t)
+    l2, q2, info = run_plan(plan, ns, A)
+    lam_o, _, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    assert np.abs(l2.cpu().numpy() - lam_o).max() <= 1e-5
+    assert int(info.abs().sum()) == 0
+
+
+def test_plan_create_refused_during_capture(uneven):
+    ns, _, flat = uneven
+    A = torch.from_numpy(flat[: ns[0] * ns[0]]).to(DEV)
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(bed.BedError) as ei:
+        with torch.cuda.graph(g):
+            bed.Plan(torch.float32, [3, 5, 7])
+    assert ei.value.status == 5  # BED_ERR_CAPTURE
