@@ -3,9 +3,16 @@
 A step is one solve (eigenvalues + eigenvectors) of the batch-512 FP32 n=64
 workload: half Gaussian symmetric (G+G^T)/2, half covariance X^T X/(4n), 10%
 of the matrices with a planted eigenvalue pair 1e-6 apart.  Inputs are resident
-in HBM before timing starts.  The same run times n=32 and n=48 (reported under
-"per_n"), a short serving loop (p50/p99 latency), and the binary64 oracle on
-the host cores ("cpu_baseline").
+in HBM before timing starts.  The same run also measures
+
+  per_n         the batch-512 workload at n=32 and n=48;
+  uneven        4096 matrices with n ~ U{4..64}: autotuned plan replayed from a
+                HIP graph vs one plain launch per distinct n;
+  backward      batch 1024, n=32 forward + backward (eigengaps >= 1e-3);
+  serving       a Poisson trace of requests (1-256 matrices, n in {8,..,64})
+                through the continuous-batching server at 0.5 and 0.9 of the
+                closed-loop saturation rate, vs plain sequential launches;
+  cpu_baseline  the binary64 oracle on the host cores, on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -20,14 +27,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (and FP32 MFMA) peak
+# MI355X FP32 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2 (dual
+# issue / packed FP32) x 2.4 GHz = 157.3 TFLOP/s; FP32 MFMA has the same figure.
+PEAK_FP32_TFLOPS = 157.3
 BATCH = 512
 
 
-def flop_model(n):
-    """Algorithmic flops of one n x n solve (fixed model, no deflation credit):
-    4/3 n^3 tridiagonalization + 2 n^3 back-transform + sum over merges of
-    2 m (m1^2 + m2^2) back-multiplication + 54 m^2 secular/Loewner work."""
+def merge_tree(n):
+    """(m, m1, m2) of every merge of the dyadic tearing tree of size n."""
     merges = []
 
     def walk(d, j):
@@ -40,33 +47,76 @@ def flop_model(n):
         walk(d + 1, 2 * j + 1)
 
     walk(0, 0)
+    return merges
+
+
+def flop_model(n):
+    """Algorithmic flops of one n x n solve (fixed model, no deflation credit):
+    4/3 n^3 tridiagonalization + 2 n^3 back-transform + sum over merges of
+    2 m (m1^2 + m2^2) back-multiplication + 54 m^2 secular/Loewner work."""
+    merges = merge_tree(n)
     gemm = sum(2 * m * (m1 * m1 + m2 * m2) for m, m1, m2 in merges)
     sec = sum(54 * m * m for m, _, _ in merges)
     return 4.0 / 3.0 * n ** 3 + 2.0 * n ** 3 + gemm + sec
 
 
-def time_solver(bed, torch, A, steps, warmup):
-    """Returns (ms per step by wall clock, ms per launch by HIP events)."""
-    b, n = A.shape[0], A.shape[1]
-    lam = torch.empty(b, n, device=A.device, dtype=A.dtype)
-    Q = torch.empty_like(A)
-    info = torch.empty(b, dtype=torch.int32, device=A.device)
-    flat, lflat = A.view(-1), lam.view(-1)
-    qflat = Q.view(-1)
-    nl = [n] * b
+def backward_flops(n):
+    """dA = Q (diag(dlam) + sym(F o Q^T dQ)) Q^T: three n x n x n products."""
+    return 6.0 * n ** 3
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch from the committed counter summary profiles/<name>.md,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name + ".md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.split(" = ", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv["kernel_sources"].split():
+            with open(os.path.join(ROOT, "paper_2604_27325_amd", "csrc", src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != kv["kernel_sources_sha256"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
+def timed(torch, fn, steps, warmup, stream=None):
+    """(wall ms per step, event ms per step) of `steps` calls of fn() after
+    `warmup` untimed ones, events on `stream` (torch's current stream if None)."""
     for _ in range(warmup):
-        bed.syevd_packed(nl, flat, lam=lflat, Q=qflat, info=info)
+        fn()
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
+    stream = stream or torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
-        bed.syevd_packed(nl, flat, lam=lflat, Q=qflat, info=info)
+        fn()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    ev = e0.elapsed_time(e1) / steps
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def time_solver(bed, torch, A, steps, warmup):
+    """Returns (ms per step by wall clock, ms per launch by HIP events, outputs)."""
+    b, n = A.shape[0], A.shape[1]
+    lam = torch.empty(b, n, device=A.device, dtype=A.dtype)
+    Q = torch.empty_like(A)
+    info = torch.empty(b, dtype=torch.int32, device=A.device)
+    flat, lflat, qflat = A.view(-1), lam.view(-1), Q.view(-1)
+    nl = [n] * b
+    wall, ev = timed(torch, lambda: bed.syevd_packed(nl, flat, lam=lflat, Q=qflat, info=info),
+                     steps, warmup)
     return wall, ev, lam, Q, info
 
 
@@ -95,42 +145,201 @@ def cpu_baseline(oracle, A_np, budget_s):
         if el >= budget_s:
             break
     return {"value": done / el, "unit": "eigendecomps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} matrices of the n={A_np.shape[1]} FP32 workload (promoted to "
-                      f"FP64), {el:.1f} s single-threaded"}
+            "sample": f"{done} matrices of the batch-512 n={A_np.shape[1]} FP32 workload "
+                      f"(promoted to FP64), {el:.1f} s single-threaded"}
 
 
-def serving_leg(bed, torch, requests, qps, seed=5000):
-    """Open-loop Poisson trace through the continuous-batching server."""
+def uneven_leg(bed, torch, steps, warmup):
+    """4096 FP32 matrices, n ~ U{4..64}: autotuned persistent plan replayed from
+    a HIP graph, against one plain bed_syevd launch per distinct n."""
     from paper_2604_27325_amd import workloads
-    arr, counts, ns = workloads.serving_trace(seed=seed, requests=requests, qps=qps)
-    bufs = []
-    for i in range(requests):
-        A = torch.from_numpy(workloads.serving_matrices(seed + 1 + i, int(counts[i]), int(ns[i])))
-        bufs.append(A.to("cuda"))
-    outs = [(torch.empty(b.shape[0], b.shape[1], device="cuda"), torch.empty_like(b)) for b in bufs]
+    ns, mats = workloads.uneven()
+    ns_list = [int(v) for v in ns]
+    _, flat = workloads.pack(mats)
+    A = torch.from_numpy(flat).to("cuda")
+    lam = torch.empty(int(ns.sum()), device="cuda")
+    Q = torch.empty_like(A)
+    info = torch.empty(len(ns_list), dtype=torch.int32, device="cuda")
+    tune = bed.autotune(torch.float32, ns_list, A, lam, Q)
+    plan = bed.Plan(torch.float32, ns_list, tune=tune)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.run(A, lam, Q, info, stream=s)
     torch.cuda.synchronize()
-    srv = bed.Server(streams=4)
-    tickets = []
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.run(A, lam, Q, info, stream=s)
+    torch.cuda.synchronize()
+    wall_g, ev_g = timed(torch, g.replay, steps, warmup)
+    wall_p, ev_p = timed(torch, lambda: plan.run(A, lam, Q, info), steps, warmup)
+    # per-size plain launches on contiguous per-n buffers
+    groups = {}
+    for i, n in enumerate(ns_list):
+        groups.setdefault(n, []).append(mats[i])
+    per = []
+    for n, ms in sorted(groups.items()):
+        An = torch.from_numpy(np.stack(ms)).to("cuda")
+        per.append((An, torch.empty(An.shape[0], n, device="cuda"), torch.empty_like(An)))
+
+    def plain():
+        for An, ln, Qn in per:
+            bed.syevd_packed([An.shape[1]] * An.shape[0], An.view(-1), lam=ln.view(-1),
+                             Q=Qn.view(-1))
+
+    wall_s, ev_s = timed(torch, plain, steps, warmup)
+    flops = sum(flop_model(n) for n in ns_list)
+    b = len(ns_list)
+    return {"matrices": b, "distinct_n": len(groups), "schedule": tune,
+            "graph": {"eigendecomps_per_s": b / (wall_g * 1e-3), "ms_per_step": wall_g,
+                      "kernel_ms": ev_g, "tflops_model": flops / (ev_g * 1e-3) / 1e12},
+            "plan_eager": {"eigendecomps_per_s": b / (wall_p * 1e-3), "ms_per_step": wall_p},
+            "per_size_plain": {"eigendecomps_per_s": b / (wall_s * 1e-3), "ms_per_step": wall_s,
+                               "launches": len(groups)},
+            "speedup_vs_per_size": wall_s / wall_g}
+
+
+def backward_leg(bed, torch, steps, warmup):
+    """Batch 1024 FP32 n=32 (eigengaps >= 1e-3): forward, backward, both."""
+    from paper_2604_27325_amd import workloads
+    A_np, dlam_np, dQ_np, _ = workloads.differentiation()
+    A = torch.from_numpy(A_np).to("cuda")
+    dlam, dQ = torch.from_numpy(dlam_np).to("cuda"), torch.from_numpy(dQ_np).to("cuda")
+    lam, Q = bed.syevd(A)
+    dA = torch.empty_like(A)
+    b, n = A.shape[0], A.shape[1]
+    nl = [n] * b
+
+    def fwd():
+        bed.syevd_packed(nl, A.view(-1), lam=lam.view(-1), Q=Q.view(-1))
+
+    def bwd():
+        bed.syevd_backward(lam, Q, dlam, dQ, out=dA)
+
+    def both():
+        fwd()
+        bwd()
+
+    wall_f, ev_f = timed(torch, fwd, steps, warmup)
+    wall_b, ev_b = timed(torch, bwd, steps, warmup)
+    wall_fb, _ = timed(torch, both, steps, warmup)
+    return {"batch": b, "n": n,
+            "forward_ms": wall_f, "backward_ms": wall_b, "backward_kernel_ms": ev_b,
+            "forward_backward_ms": wall_fb,
+            "eigendecomps_per_s_fwd_bwd": b / (wall_fb * 1e-3),
+            "backward_tflops": b * backward_flops(n) / (ev_b * 1e-3) / 1e12}
+
+
+class _ServeData:
+    """Per-request input views into per-n pools and private output buffers."""
+
+    def __init__(self, torch, counts, ns, seed):
+        from paper_2604_27325_amd import workloads
+        pool_sz = 1024
+        self.pools = {}
+        for n in sorted(set(int(v) for v in ns)):
+            self.pools[n] = torch.from_numpy(
+                workloads.serving_matrices(seed + n, pool_sz, n)).to("cuda")
+        rng = np.random.default_rng(seed)
+        lam_tot = int(np.sum(counts.astype(np.int64) * ns))
+        q_tot = int(np.sum(counts.astype(np.int64) * ns * ns))
+        self.lam_all = torch.empty(lam_tot, device="cuda")
+        self.q_all = torch.empty(q_tot, device="cuda")
+        self.req = []
+        ol = oq = 0
+        for c, n in zip(counts.tolist(), ns.tolist()):
+            off = int(rng.integers(0, pool_sz - c + 1))
+            A = self.pools[n][off:off + c]
+            lam = self.lam_all[ol:ol + c * n].view(c, n)
+            Q = self.q_all[oq:oq + c * n * n].view(c, n, n)
+            self.req.append((A, lam, Q))
+            ol += c * n
+            oq += c * n * n
+
+
+def _serve_server(bed, data, arrivals, streams=4):
+    """Open loop through the server (arrivals=None: closed loop, all at t=0).
+    Latency = arrival -> completion observed by the server's scheduler."""
+    srv = bed.Server(streams=streams)
+    R = len(data.req)
+    arr = np.zeros(R) if arrivals is None else arrivals
+    tickets, sub = [], np.zeros(R)
     t0 = time.perf_counter()
-    for i in range(requests):
+    for i in range(R):
         while time.perf_counter() - t0 < arr[i]:
             pass
-        tk = None
+        A, lam, Q = data.req[i]
+        tk = srv.submit(A, lam, Q)
         while tk is None:
-            tk = srv.submit(bufs[i], outs[i][0], outs[i][1])
+            tk = srv.submit(A, lam, Q)
+        sub[i] = time.perf_counter() - t0
         tickets.append(tk)
     srv.drain()
     el = time.perf_counter() - t0
-    lats = []
-    for tk in tickets:
-        done, lat = srv.poll(tk)
-        lats.append(lat)
+    lats = np.empty(R)
+    for i, tk in enumerate(tickets):
+        done, lat_us = srv.poll(tk)
+        lats[i] = (sub[i] - arr[i]) * 1e3 + lat_us * 1e-3
     srv.close()
-    lats = np.asarray(lats)
+    return el, lats
+
+
+def _serve_plain(bed, torch, data, arrivals):
+    """The same trace as plain sequential bed_syevd calls on one stream;
+    latency = arrival -> completion event observed on the host."""
+    R = len(data.req)
+    s = torch.cuda.Stream()
+    evs = [None] * R
+    done_t = np.zeros(R)
+    head = 0
+    t0 = time.perf_counter()
+
+    def reap(upto):
+        nonlocal head
+        while head < upto and evs[head].query():
+            done_t[head] = time.perf_counter() - t0
+            head += 1
+
+    with torch.cuda.stream(s):
+        for i in range(R):
+            while time.perf_counter() - t0 < arrivals[i]:
+                reap(i)
+            A, lam, Q = data.req[i]
+            bed.syevd_packed([A.shape[1]] * A.shape[0], A.reshape(-1), lam=lam.reshape(-1),
+                             Q=Q.reshape(-1), stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+            evs[i] = ev
+            reap(i)
+        while head < R:
+            reap(R)
+    el = time.perf_counter() - t0
+    return el, (done_t - arrivals) * 1e3
+
+
+def serving_leg(bed, torch, requests, fracs=(0.5, 0.9), seed=5000):
+    """Saturation rate from a closed loop, then open-loop Poisson traces at
+    fractions of it, through the server and through plain sequential launches."""
+    from paper_2604_27325_amd import workloads
+    _, counts, ns = workloads.serving_trace(seed=seed, requests=requests, qps=1.0)
+    data = _ServeData(torch, counts, ns, seed + 1)
     mats = int(np.sum(counts))
-    return {"requests": requests, "qps_offered": qps, "matrices": mats,
-            "matrices_per_s": mats / el, "p50_ms": float(np.percentile(lats, 50) / 1e3),
-            "p99_ms": float(np.percentile(lats, 99) / 1e3)}
+    _serve_server(bed, data, None)  # warm-up
+    el, _ = _serve_server(bed, data, None)
+    r_sat = requests / el
+    out = {"requests": requests, "matrices": mats, "saturation_requests_per_s": r_sat,
+           "saturation_matrices_per_s": mats / el, "loads": []}
+    for f in fracs:
+        arr, _, _ = workloads.serving_trace(seed=seed, requests=requests, qps=f * r_sat)
+        el_s, lat_s = _serve_server(bed, data, arr)
+        el_p, lat_p = _serve_plain(bed, torch, data, arr)
+        out["loads"].append({
+            "fraction_of_saturation": f, "qps_offered": f * r_sat,
+            "server": {"matrices_per_s": mats / el_s, "p50_ms": float(np.percentile(lat_s, 50)),
+                       "p99_ms": float(np.percentile(lat_s, 99))},
+            "plain_sequential": {"matrices_per_s": mats / el_p,
+                                 "p50_ms": float(np.percentile(lat_p, 50)),
+                                 "p99_ms": float(np.percentile(lat_p, 99))}})
+    return out
 
 
 def main():
@@ -141,9 +350,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-qps", type=float, default=1000.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the batch-512 legs (no uneven / backward / serving)")
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--only-n", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also launch one 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver shards by matrix with no "
@@ -156,6 +368,13 @@ def main():
     from paper_2604_27325_amd import workloads
 
     bed.load_library()
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {src.numel() * 4} bytes read, "
+              f"{dst.numel() * 4} bytes written", flush=True)
     per_n = {}
     main_res = None
     sizes = [args.only_n] if args.only_n else [32, 48, 64]
@@ -167,6 +386,8 @@ def main():
         per_n[str(n)] = {"eigendecomps_per_s": BATCH / (wall * 1e-3), "ms_per_step": wall,
                          "kernel_ms": ev, "tflops_model": BATCH * F / (ev * 1e-3) / 1e12,
                          "flops_per_matrix": F}
+        print(f"[bench] n={n}: {per_n[str(n)]['eigendecomps_per_s']:.4g} matrices/s, "
+              f"kernel {ev * 1e3:.1f} us", flush=True)
         if n == sizes[-1]:
             main_res = (n, A_np, wall, ev, lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy())
 
@@ -175,12 +396,21 @@ def main():
     achieved = BATCH * F / (ev * 1e-3) / 1e12
     import oracle
     parity = parity_sample(oracle, A_np, lam, Q, info)
+    uneven = backward = serving = None
+    if not args.no_extra:
+        uneven = uneven_leg(bed, torch, max(args.steps // 4, 10), max(args.warmup // 4, 3))
+        print(f"[bench] uneven: graph {uneven['graph']['eigendecomps_per_s']:.4g} matrices/s, "
+              f"{uneven['speedup_vs_per_size']:.2f}x per-size launches", flush=True)
+        backward = backward_leg(bed, torch, args.steps, args.warmup)
+        print(f"[bench] backward: {backward['backward_kernel_ms'] * 1e3:.1f} us", flush=True)
+        if not args.no_serve:
+            serving = serving_leg(bed, torch, args.serve_requests)
+            print(f"[bench] serving: saturation {serving['saturation_matrices_per_s']:.4g} "
+                  "matrices/s", flush=True)
     cpu = None if args.no_cpu else cpu_baseline(oracle, A_np, args.cpu_seconds)
-    serving = None if args.no_serve else serving_leg(bed, torch, args.serve_requests,
-                                                     args.serve_qps)
     line = {
         "metric": "eigendecomps/sec at n=64 fp32 batch 512 (n=32, n=48 under per_n; "
-                  "p50/p99 under serving)",
+                  "p50/p99 latency under serving)",
         "value": BATCH / (wall * 1e-3),
         "unit": "eigendecomps/s",
         "n_gpus": 1,
@@ -196,12 +426,15 @@ def main():
                                "half covariance X^T X/(4n), 10% planted 1e-6 eigenpairs",
                    "batch": BATCH, "n": n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_syevd_uniform<float,64,256>",
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": profiled_traffic(f"k_syevd_uniform_f32_n{n}_b{BATCH}"),
+                     "kernel": f"k_syevd_uniform<float, {n}, 256>",
                      "flops_per_launch": BATCH * F, "kernel_ms": ev},
         "cpu_baseline": cpu,
         "per_n": per_n,
         "parity": parity,
+        "uneven": uneven,
+        "backward": backward,
         "serving": serving,
     }
     print(json.dumps(line))

@@ -169,9 +169,9 @@ def syevals(A, stream=None):
     return lam[0] if A.dim() == 2 else lam
 
 
-def syevd_backward(lam, Q, dlam=None, dQ=None, eps=0.0, n_list=None, stream=None):
+def syevd_backward(lam, Q, dlam=None, dQ=None, eps=0.0, n_list=None, stream=None, out=None):
     """dA = Q (diag(dlam) + sym(F o Q^T dQ)) Q^T (uniform (batch, n[, n]) tensors,
-    or flat packed tensors with n_list)."""
+    or flat packed tensors with n_list).  `out` (Q's shape) receives dA."""
     import torch
     lib = load_library()
     if n_list is None:
@@ -181,7 +181,9 @@ def syevd_backward(lam, Q, dlam=None, dQ=None, eps=0.0, n_list=None, stream=None
     lam_c, Q_c = lam.contiguous(), Q.contiguous()
     dl = dlam.contiguous() if dlam is not None else None
     dq = dQ.contiguous() if dQ is not None else None
-    dA = torch.empty_like(Q_c)
+    dA = torch.empty_like(Q_c) if out is None else out
+    if dA.shape != Q_c.shape or dA.dtype != Q_c.dtype:
+        raise ValueError("out must have Q's shape and dtype")
     _check(lib.bed_syevd_backward(
         _dtype_code(Q.dtype), len(n_arr), n_ptr, _dev(lam_c, "lambda"), _dev(Q_c, "Q"),
         _dev(dl, "dlambda") if dl is not None else None,
