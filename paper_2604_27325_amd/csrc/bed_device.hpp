@@ -43,6 +43,10 @@ __device__ __forceinline__ float f_rcp(float x)
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 __device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
+// Hardware reciprocal alone (about 1 ulp in FP32): for sums whose own
+// rounding dominates, such as the secular function's terms.
+__device__ __forceinline__ float f_rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double f_rcp_fast(double x) { return 1.0 / x; }
 __device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float f_div(float a, float b) { return a * f_rcp(b); }
@@ -203,6 +207,19 @@ template <typename T> __device__ __forceinline__ T wave_prefix_sum(T x)
     x += dppm<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
     x += dppm<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return x;
+}
+
+// Sum over the whole wave, returned as a wave-uniform value: row sums by four
+// DPP butterflies, rows combined by the two row broadcasts into lane 63.
+template <typename T> __device__ __forceinline__ T wave_total(T x)
+{
+    x += xmove<1>(x, 0);
+    x += xmove<2>(x, 0);
+    x += xmove<4>(x, 0);
+    x += xmove<8>(x, 0);
+    x += dppm<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dppm<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return bcast(x, 63);
 }
 
 // Bits [lo, hi) of a 64-bit lane mask.

@@ -29,6 +29,9 @@
 #ifndef BED_COUNT
 #define BED_COUNT(id, value) ((void)0)
 #endif
+#ifndef BED_ROOT
+#define BED_ROOT(depth, root, evals, reason) ((void)0)
+#endif
 
 namespace bed {
 
@@ -63,6 +66,7 @@ struct Smem {
             T zh[NMAX], rnrm[NMAX];
             T rc[NMAX], rs[NMAX];
             int rpart[NMAX];
+            int rlist[NMAX], nrot[NMAX];  // per node: deflated index of each rotation, in scan order
             int col[NMAX];
             int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
             int ckl[NMAX], ckh[NMAX];  // child block of each row of a merged node
@@ -189,6 +193,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             z2[j] = ok ? zv * zv : T(0);
         }
         int o = jr, state = 0, nmulti = 0, nhal = 0;
+        T ao = live ? rho * zk[jr] * zk[jr] : T(0);  // rho z_o^2 of the origin pole
         bool done = !live, capped = false;
         T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
         T dorg = live ? dk[jr] : T(0);
@@ -213,17 +218,18 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
         }
 #pragma unroll
         for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
-        int rounds = 0;
+        int rounds = 0, nev = 0, why = 0;
         // Progressive removal (Eq. (22)): a converged root's lanes idle; the
         // wave leaves the loop once all of its roots have stopped.
         while (__ballot(!done)) {
             ++rounds;
             if (!done) {
+                ++nev;
                 // Eq. (8), (18), (21) at h: delta_i = (d_i - d_o) - h
                 T s0 = 0, s1 = 0, s2 = 0, e = 0;
 #pragma unroll
                 for (int j = 0; j < KPL; ++j) {
-                    const T rinv = f_rcp(df[j] - h);
+                    const T rinv = f_rcp_fast(df[j] - h);
                     const T t0 = z2[j] * rinv;
                     const T t1 = t0 * rinv;
                     s0 += t0;
@@ -247,6 +253,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
                 } else if (state == 1 || state == 2) {  // bisection / multi-section
                     if (f == T(0)) {
                         done = true;
+                        why = 1;
                     } else {
                         if (state == 1) {
                             if (jr < kq - 1) {
@@ -256,6 +263,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
                                 } else {
                                     o = jr + 1;  // root nearer d_{j+1}: shift origin
                                     dorg = dk[jr + 1];
+                                    ao = rho * zk[jr + 1] * zk[jr + 1];
 #pragma unroll
                                     for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
                                     L = h - gap;
@@ -287,25 +295,43 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
                 } else {  // Halley, Eq. (20), safeguarded by the bracket
                     if (f_abs(f) <= eb) {
                         done = true;
+                        why = 2;
                     } else {
                         if (f > T(0)) U = h;
                         else L = h;
                         if (U - L <= T(2) * u * (f_abs(L) + f_abs(U))) {
                             done = true;
+                            why = 3;
                         } else {
                             const T den = T(2) * f1 * f1 - f * f2;
                             T hn = T(0.5) * (L + U);
+                            bool ok = false;
                             if (den > T(0) && f_finite(den)) {
                                 const T cand = h - T(2) * f * f1 * f_rcp(den);
-                                if (cand > L && cand < U) hn = cand;
+                                ok = cand > L && cand < U;
+                                if (ok) hn = cand;
+                            }
+                            if (!ok) {
+                                // Safeguard: root of the one-pole model
+                                // f ~ c - ao/tau through (h, f), ao = rho z_o^2 of
+                                // the origin pole; a plain bisection if it leaves
+                                // the bracket.  Converges where Halley's local
+                                // model fails next to a light origin pole.
+                                const T den2 = fma(f, h, ao);
+                                if (den2 != T(0)) {
+                                    const T cand = ao * h * f_rcp(den2);
+                                    if (cand > L && cand < U) hn = cand;
+                                }
                             }
                             if (hn == h) {
                                 done = true;
+                                why = 4;
                             } else {
                                 h = hn;
                                 if (++nhal >= SEC_CAP) {
                                     done = true;
                                     capped = true;
+                                    why = 5;
                                 }
                             }
                         }
@@ -314,6 +340,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             }
         }
         BED_COUNT(d, rounds);
+        if (live && sub == 0) BED_ROOT(d, q, nev, why);
         if (live && sub == 0) {
             S.u.m.rdo[q] = dorg;
             S.u.m.rtau[q] = h;
@@ -410,9 +437,9 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
         // Type-2 rotations act on the rows of M in reverse scan order.
         if (qact && sub == 0) {
             const int c = qlo + jr;
-            for (int p = qn.hi - 1; p >= qlo; --p) {
+            for (int i = S.u.m.nrot[qlo] - 1; i >= 0; --i) {
+                const int p = S.u.m.rlist[qlo + i];
                 const int part = S.u.m.rpart[p];
-                if (part < 0) continue;
                 const int rp = S.u.m.sperm[p], ri = S.u.m.sperm[part];
                 const T cc = S.u.m.rc[p], ss = S.u.m.rs[p];
                 const T mp = S.M[rp * LD + c], mi = S.M[ri * LD + c];
@@ -437,6 +464,161 @@ __device__ __forceinline__ void roots_vectors_dispatch(Smem<T, NMAX, NT>& S, con
         else
             roots_vectors_dispatch<T, NMAX, NT, KPL * 2>(S, n, d, t, Ln, need);
     }
+}
+
+// Householder tridiagonalization by one wave (FP32).  Lane (r, g), g < G =
+// 64/NMAX, keeps row r of the columns c = g + G j, j < CPT, in registers; p = A v
+// is a per-lane dot product plus a butterfly over the G column groups, so a
+// step needs no barrier and no cross-wave exchange.  Steps whose dead columns
+// (c <= k, where v_c = 0) fill the first Q0 chunks of four registers run in the
+// instance for that Q0, whose chunk range is a compile-time constant.
+//
+// Software pipeline: step k forms the updated pivot column k+1 and its norm
+// directly, then the reflector of step k+1 (alpha, tau, v, its LDS broadcast)
+// and only after that issues its own rank-2 update, so the dependent scalar
+// chain and the reductions of step k+1 overlap the update's FMAs.
+template <typename T>
+struct HhRefl {
+    T alpha, tau, rv0;
+};
+template <typename T>
+__device__ __forceinline__ HhRefl<T> hh_reflector(const T x0, const T sig)
+{
+    // alpha = -sgn(x0) ||x||, v = (1, x_2.. / (x0 - alpha)), tau = 2 / (v^T v) of
+    // the v actually formed; tau = 0 when the sub-column is already zero
+    const bool z = (sig == T(0));
+    const T mu = f_sqrt(x0 * x0 + sig);
+    HhRefl<T> h;
+    h.alpha = z ? x0 : ((x0 < T(0)) ? mu : -mu);
+    const T rv = f_rcp(x0 - h.alpha);
+    h.rv0 = z ? T(1) : rv;
+    const T tv = T(2) * f_rcp(T(1) + sig * h.rv0 * h.rv0);
+    h.tau = z ? T(0) : tv;
+    return h;
+}
+
+template <typename T, int NMAX, int NT, int Q0>
+__device__ __forceinline__ void hh_wave_range(Smem<T, NMAX, NT>& S, const int n, const int lane,
+                                              T (&ar)[NMAX * NMAX / 64], T& xr, T& sig, T& vr,
+                                              T& tauk)
+{
+    constexpr int G = 64 / NMAX;
+    constexpr int CPT = NMAX / G;
+    constexpr int NCH = CPT / 4;
+    const int r = lane % NMAX, g = lane / NMAX;
+    const bool g0 = lane < NMAX;
+    const int pos_r = (r % G) * CPT + r / G;
+    T* vb = S.u.h.vbuf;
+    T* wb = S.u.h.wbuf;
+    const int kb = (Q0 == 0) ? 0 : 4 * G * Q0 - 1;
+    const int ke = min(4 * G * (Q0 + 1) - 1, n - 2);
+    // loop invariant: vr, tauk and the LDS copy of v belong to step k; ar holds
+    // the matrix after steps < k
+    for (int k = kb; k < ke; ++k) {
+        wave_sync();
+        T vc[CPT];
+#pragma unroll
+        for (int j = 4 * Q0; j < CPT; ++j) vc[j] = vb[g * CPT + j];
+        T pp0 = T(0), pp1 = T(0);
+#pragma unroll
+        for (int q = Q0; q < NCH; ++q) {
+            pp0 = fma(ar[4 * q + 0], vc[4 * q + 0], pp0);
+            pp1 = fma(ar[4 * q + 1], vc[4 * q + 1], pp1);
+            pp0 = fma(ar[4 * q + 2], vc[4 * q + 2], pp0);
+            pp1 = fma(ar[4 * q + 3], vc[4 * q + 3], pp1);
+        }
+        T pr = pp0 + pp1;
+        if constexpr (G >= 4) pr += xmove<16>(pr, lane);
+        if constexpr (G >= 2) pr += xmove<32>(pr, lane);
+        pr *= tauk;
+        const T pv = wave_total(g0 ? pr * vr : T(0));
+        const T wr = pr - T(0.5) * tauk * pv * vr;
+        if (g0) wb[pos_r] = wr;
+        wave_sync();
+        T wc[CPT];
+#pragma unroll
+        for (int j = 4 * Q0; j < CPT; ++j) wc[j] = wb[g * CPT + j];
+        // pivot column k + 1 after this step, from its owner group
+        const int c1 = k + 1;
+        const int g1 = c1 % G;
+        const int pos1 = g1 * CPT + c1 / G;
+        const T v1 = vb[pos1], w1 = wb[pos1];
+        // in this instance c1 / G lies in [4 Q0, 4 Q0 + 4)
+        const T a1 = pick<4>(ar + 4 * Q0, (c1 / G) & 3);
+        const T xo = fma(-wr, v1, fma(-vr, w1, a1));  // valid in group g1
+        T xn = xo;
+        if constexpr (G == 2) {
+            const T o32 = xmove<32>(xo, lane);
+            xn = (g == g1) ? xo : o32;
+        } else if constexpr (G == 4) {
+            const T o16 = xmove<16>(xo, lane);
+            const T o32 = xmove<32>(xo, lane);
+            const T o48 = xmove<32>(o16, lane);
+            const int dd = g ^ g1;
+            xn = dd == 0 ? xo : (dd == 1 ? o16 : (dd == 2 ? o32 : o48));
+        }
+        const T sn = wave_total((g0 && r > k + 2) ? xn * xn : T(0));
+        // reflector of step k + 1 (harmless past the last step: nothing reads
+        // reflector n - 2, and b[n - 2], a[n - 2] are rewritten afterwards)
+        const HhRefl<T> h = hh_reflector(bcast(xn, k + 2), sn);
+        const T vn = (r == k + 2) ? T(1) : ((r > k + 2 && sn != T(0)) ? xn * h.rv0 : T(0));
+        if (lane == 0) {
+            S.tau[k + 1] = h.tau;
+            S.b[k + 1] = h.alpha;
+        }
+        if (g0) {
+            if (r == k + 1) S.a[k + 1] = xn;
+            S.Vt[(k + 1) * NMAX + r] = vn;
+            vb[pos_r] = vn;
+        }
+        // rank-2 update of step k
+#pragma unroll
+        for (int j = 4 * Q0; j < CPT; ++j) ar[j] = fma(-wr, vc[j], fma(-vr, wc[j], ar[j]));
+        xr = xn;
+        sig = sn;
+        vr = vn;
+        tauk = h.tau;
+    }
+    if constexpr (Q0 + 1 < NCH) hh_wave_range<T, NMAX, NT, Q0 + 1>(S, n, lane, ar, xr, sig, vr, tauk);
+}
+
+template <typename T, int NMAX, int NT>
+__device__ __forceinline__ void householder_wave(Smem<T, NMAX, NT>& S, const int n, const int lane)
+{
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int G = 64 / NMAX;
+    constexpr int CPT = NMAX / G;
+    static_assert(CPT % 4 == 0, "chunks of four columns");
+    const int r = lane % NMAX, g = lane / NMAX;
+    const bool g0 = lane < NMAX;
+    T ar[CPT];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = g + G * j;
+        ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
+    }
+    T xr = (r < n) ? S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
+    T sig = wave_total((g0 && r > 1) ? xr * xr : T(0));
+    // reflector of step 0 (harmless when n <= 2, as above)
+    const HhRefl<T> h = hh_reflector(bcast(xr, 1), sig);
+    T vr = (r == 1) ? T(1) : ((r > 1 && sig != T(0)) ? xr * h.rv0 : T(0));
+    T tauk = h.tau;
+    if (lane == 0) {
+        S.tau[0] = h.tau;
+        S.b[0] = h.alpha;
+    }
+    if (g0) {
+        if (r == 0) S.a[0] = xr;
+        S.Vt[r] = vr;
+        S.u.h.vbuf[(r % G) * CPT + r / G] = vr;
+    }
+    hh_wave_range<T, NMAX, NT, 0>(S, n, lane, ar, xr, sig, vr, tauk);
+    wave_sync();
+    if (g0 && n >= 2) {
+        if (r == n - 2) S.a[n - 2] = xr;
+        if (r == n - 1) S.b[n - 2] = xr;
+    }
+    if (g == (n - 1) % G && r == n - 1) S.a[n - 1] = pick<CPT>(ar, (n - 1) / G);
 }
 
 template <typename T, int NMAX, int NT>
@@ -490,19 +672,36 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     BED_PHASE(1);
 
     // ------------------------------------------------------------ Householder
-    // Thread (r, g) keeps A[r][g*CPT .. g*CPT+CPT) in registers.  Each step k
-    // uses one team barrier: the partial products of p = A v and the
+    // FP32 teams of up to four waves reduce on one wave (its row block fits
+    // the register budget of two resident teams per SIMD); otherwise the team
+    // shares the columns.
+    if constexpr (sizeof(T) == 4 && NT <= 256) {
+        if (wave == 0) householder_wave<T, NMAX, NT>(S, n, lane);
+    } else
+    // Thread (r, g) keeps row r of the columns c = g + G j (j < CPT) in
+    // registers: a cyclic split, so every column group shrinks at the same
+    // rate as the trailing matrix does and whole chunks of dead columns
+    // (c <= k, where v_c = 0) are skipped by wave-uniform branches.  Each step
+    // k uses one team barrier: the partial products of p = A v and the
     // pre-update pivot column k+1 cross waves together; every wave then forms
     // w and the next pivot column on its own (a look-ahead of one column).
+    // v and w reach the column groups through per-wave LDS vectors stored
+    // group-major (column c at (c % G) CPT + c / G), one 16-byte read per chunk.
     {
-        T ar[CPT];
+        static_assert(CPT % 4 == 0, "Householder chunks of four columns");
+        constexpr int NCH = CPT / 4;
+        constexpr int GPW = 64 / NMAX < 1 ? 1 : 64 / NMAX;  // column groups per wave
+        typedef T colvec __attribute__((ext_vector_type(CPT)));
+        colvec ar;
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
-            const int c = g * CPT + j;
+            const int c = g + G * j;
             ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
         }
-        T xr = (r < n) ? S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
+        const int g_last = wave * GPW + GPW - 1;  // last column group of this wave
+        T xr = (r < n) ? S.M[r * LD] : T(0);     // pivot column 0 (lower triangle)
         const bool elem = lane < NMAX;
+        const int pos_r = (r % G) * CPT + r / G;  // group-major slot of index r
         for (int k = 0; k + 2 < n; ++k) {
             if (t == k) S.a[k] = xr;
             const T x0 = bcast(xr, k + 1);
@@ -518,7 +717,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 rv0 = f_rcp(x0 - alpha);
                 // tau = 2 / (v^T v) of the v actually formed (v_0 = 1, v_i = x_i rv0),
                 // so each reflector is orthogonal to rounding whatever rv0's error
-                tauk = T(2) / (T(1) + sig * rv0 * rv0);
+                tauk = T(2) * f_rcp(T(1) + sig * rv0 * rv0);
             }
             const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr * rv0 : T(0));
             if (t == 0) {
@@ -526,23 +725,31 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 S.b[k] = alpha;
             }
             if (g == 0) S.Vt[k * NMAX + r] = vr;
-            // v of this thread's column group through the wave's LDS buffer
             T* vb = S.u.h.vbuf + wave * NMAX;
-            if (elem) vb[r] = vr;
+            if (elem) vb[pos_r] = vr;
             wave_sync();
+            const int c1 = k + 1;
+            const int pos1 = (c1 % G) * CPT + c1 / G;
+            const T v1 = vb[pos1];
+            // all reads issued before any use: one LDS wait, not one per chunk
             T vc[CPT];
 #pragma unroll
             for (int j = 0; j < CPT; ++j) vc[j] = vb[g * CPT + j];
-            T pp = T(0);
+            T pp0 = T(0), pp1 = T(0);
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) pp = fma(ar[j], vc[j], pp);
-            T* pa = S.u.h.part + (k & 1) * G * NMAX;
-            pa[g * NMAX + r] = pp;
-            {
-                const int c1 = k + 1;
-                if (g == c1 / CPT) S.u.h.colb[(k & 1) * NMAX + r] = pick<CPT>(ar, c1 - g * CPT);
+            for (int q = 0; q < NCH; ++q) {
+                if (g_last + G * (4 * q + 3) > k) {  // chunk has a live column
+                    pp0 = fma(ar[4 * q + 0], vc[4 * q + 0], pp0);
+                    pp1 = fma(ar[4 * q + 1], vc[4 * q + 1], pp1);
+                    pp0 = fma(ar[4 * q + 2], vc[4 * q + 2], pp0);
+                    pp1 = fma(ar[4 * q + 3], vc[4 * q + 3], pp1);
+                }
             }
+            T* pa = S.u.h.part + (k & 1) * G * NMAX;
+            pa[g * NMAX + r] = pp0 + pp1;
+            if (g == c1 % G) S.u.h.colb[(k & 1) * NMAX + r] = ar[c1 / G];
             team_sync<NT>();
+            const T cb = S.u.h.colb[(k & 1) * NMAX + r];
             T pr = T(0);
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) pr += pa[gg * NMAX + r];
@@ -550,14 +757,23 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T pv = wave_sum(elem ? pr * vr : T(0), lane);
             const T wr = pr - T(0.5) * tauk * pv * vr;
             T* wb = S.u.h.wbuf + wave * NMAX;
-            if (elem) wb[r] = wr;
+            if (elem) wb[pos_r] = wr;
             wave_sync();
+            T wc[CPT];
 #pragma unroll
-            for (int j = 0; j < CPT; ++j) {
-                const T wc = wb[g * CPT + j];
-                ar[j] = fma(-wr, vc[j], fma(-vr, wc, ar[j]));
+            for (int j = 0; j < CPT; ++j) wc[j] = wb[g * CPT + j];
+            const T w1 = wb[pos1];
+#pragma unroll
+            for (int q = 0; q < NCH; ++q) {
+                if (g_last + G * (4 * q + 3) > k) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int j = 4 * q + i;
+                        ar[j] = fma(-wr, vc[j], fma(-vr, wc[j], ar[j]));
+                    }
+                }
             }
-            xr = fma(-wr, vb[k + 1], fma(-vr, wb[k + 1], S.u.h.colb[(k & 1) * NMAX + r]));
+            xr = fma(-wr, v1, fma(-vr, w1, cb));
         }
         if (n >= 2) {
             if (t == n - 2) S.a[n - 2] = xr;
@@ -565,10 +781,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         }
         {
             const int c1 = n - 1;
-            if (g == c1 / CPT) {
-                const T val = pick<CPT>(ar, c1 - g * CPT);
-                if (r == c1) S.a[n - 1] = val;
-            }
+            if (g == c1 % G && r == c1) S.a[n - 1] = ar[c1 / G];
         }
     }
     team_sync<NT>();
@@ -687,19 +900,35 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 S.u.m.sz[e] = zp;
             }
             bool hasrot = false;
+            int my_nrot = 0;
             if (cmask) {
                 // Rare path: the exact sequential Givens scan for nodes that
                 // have a type-2 candidate (one lane per such node).
                 wave_sync();
                 const bool mine = act && e == lo && (cmask & lane_range(lo, hi));
                 if (mine) {
-                    int last = -1;
-                    for (int p = lo; p < hi; ++p) {
-                        if (S.u.m.sdefl[p]) continue;
-                        if (last < 0) {
-                            last = p;
+                    // The scan over consecutive live pairs (last, p) changes
+                    // something only at a pair that passes the test.  A pair
+                    // whose `last` no rotation has touched passes exactly when
+                    // the candidate test above (same operands, same formula)
+                    // did, so only candidates and the successor of each rotated
+                    // element are visited, in ascending order.
+                    uint64_t lv = live & lane_range(lo, hi);
+                    uint64_t cm = cmask & lane_range(lo, hi);
+                    int mod = -1;  // element changed by the latest rotation
+                    for (;;) {
+                        const uint64_t after = (mod >= 0) ? (lv & ~lane_range(0, mod + 1)) : 0;
+                        const int succ = after ? __builtin_ctzll(after) : 64;
+                        const int cnd = cm ? __builtin_ctzll(cm) : 64;
+                        const int p = succ < cnd ? succ : cnd;
+                        if (p >= hi) break;
+                        cm &= ~(1ull << p);
+                        const uint64_t bl = lv & lane_range(lo, p);
+                        if (!bl) {
+                            mod = -1;
                             continue;
                         }
+                        const int last = 63 - __clzll(bl);
                         const T zl = S.u.m.sz[last], zi = S.u.m.sz[p];
                         const T dl = S.u.m.sd[last], di = S.u.m.sd[p];
                         const T rr = f_hypot(zl, zi);
@@ -713,8 +942,12 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                             S.u.m.rc[last] = c;
                             S.u.m.rs[last] = sn;
                             S.u.m.rpart[last] = p;
+                            S.u.m.rlist[lo + my_nrot++] = last;
+                            lv &= ~(1ull << last);
+                            mod = p;
+                        } else {
+                            mod = -1;
                         }
-                        last = p;
                     }
                 }
                 wave_sync();
@@ -748,6 +981,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 S.u.m.nrho[lo] = rho;
                 S.u.m.nzz[lo] = zz;
                 S.u.m.nfro[lo] = f_sqrt(f_max(fro2, T(0)));
+                S.u.m.nrot[lo] = my_nrot;
             }
             const bool anyrot = __ballot(hasrot) != 0;
             if (e == 0) S.anyrot = anyrot ? 1 : 0;
