@@ -195,8 +195,9 @@ extern "C" bed_status bed_plan_create(bed_plan **plan, bed_dtype dt, int64_t bat
     if (stream_capturing((hipStream_t)stream))
         return fail(BED_ERR_CAPTURE, "bed_plan_create while its stream is being captured");
     bed_tune t = tune ? *tune : tuned_or_default(dt, batch, n);
-    if (t.threads_big == 0) t.threads_big = 256;
-    if (t.threads_mid == 0) t.threads_mid = 64;
+    const bed_tune dflt = default_tune();
+    if (t.threads_big == 0) t.threads_big = dflt.threads_big;
+    if (t.threads_mid == 0) t.threads_mid = dflt.threads_mid;
     if (!team_supported(dt, TeamShape{64, t.threads_big}) ||
         !team_supported(dt, TeamShape{32, t.threads_mid}))
         return fail(BED_ERR_INVALID_ARG, "unsupported thread counts (%d, %d)", t.threads_big,

@@ -26,24 +26,33 @@ k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
                             info ? info + b : nullptr, S, threadIdx.x);
 }
 
+// Static schedule: workgroup b solves item b.  The hardware dispatcher
+// already hands a freed compute unit the next workgroup, so a finished team's
+// slot is refilled at once.
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_list(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
-             int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count,
-             int *counter)
+             int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count)
+{
+    __shared__ Smem<T, NMAX, NT> S;
+    if ((int)blockIdx.x >= count) return;
+    const WorkItem w = items[blockIdx.x];
+    syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
+                            info ? info + w.idx : nullptr, S, threadIdx.x);
+}
+
+// Persistent schedule: a fixed grid whose workgroups take matrices from a
+// device counter until the list is exhausted, so the batch shrinks as work
+// completes (Sec. 2.3.4, Eq. (22)).  The last workgroup to finish resets the
+// counters, so the launch can be replayed from a graph without a memset.
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
+k_syevd_persist(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
+                int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count,
+                int *counter)
 {
     __shared__ Smem<T, NMAX, NT> S;
     __shared__ int cur;
-    if (counter == nullptr) {
-        for (int it = blockIdx.x; it < count; it += gridDim.x) {
-            const WorkItem w = items[it];
-            syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
-                                    info ? info + w.idx : nullptr, S, threadIdx.x);
-        }
-        return;
-    }
-    // Persistent schedule: converged workgroups immediately take the next
-    // matrix, so the batch shrinks as work completes (Sec. 2.3.4, Eq. (22)).
     for (;;) {
         if (threadIdx.x == 0) cur = atomicAdd(&counter[0], 1);
         __syncthreads();
@@ -112,11 +121,16 @@ template <typename T>
 static hipError_t list_t(TeamShape ts, const void *A, void *lam, void *Q, int32_t *info,
                          const WorkItem *items, int count, int *counter, int grid, hipStream_t s)
 {
-#define X(NM, NTT)                                                                            \
-    if (ts.nmax == NM && ts.nt == NTT) {                                                      \
-        hipLaunchKernelGGL((k_syevd_list<T, NM, NTT>), dim3((unsigned)grid), dim3(NTT), 0, s, \
-                           (const T *)A, (T *)lam, (T *)Q, info, items, count, counter);      \
-        return hipGetLastError();                                                             \
+#define X(NM, NTT)                                                                             \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                       \
+        if (counter)                                                                           \
+            hipLaunchKernelGGL((k_syevd_persist<T, NM, NTT>), dim3((unsigned)grid), dim3(NTT), \
+                               0, s, (const T *)A, (T *)lam, (T *)Q, info, items, count,       \
+                               counter);                                                       \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_syevd_list<T, NM, NTT>), dim3((unsigned)count), dim3(NTT),   \
+                               0, s, (const T *)A, (T *)lam, (T *)Q, info, items, count);      \
+        return hipGetLastError();                                                              \
     }
     BED_SHAPES(X)
 #undef X
@@ -160,7 +174,7 @@ static int bpc_t(TeamShape ts)
     int nb = 0;
 #define X(NM, NTT)                                                                       \
     if (ts.nmax == NM && ts.nt == NTT) {                                                 \
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_syevd_list<T, NM, NTT>,  \
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_syevd_persist<T, NM, NTT>, \
                                                          NTT, 0) != hipSuccess)          \
             nb = 1;                                                                      \
         return nb > 0 ? nb : 1;                                                          \

@@ -29,6 +29,9 @@
 #ifndef BED_COUNT
 #define BED_COUNT(id, value) ((void)0)
 #endif
+#ifndef BED_MARK
+#define BED_MARK(depth, id) ((void)0)
+#endif
 #ifndef BED_ROOT
 #define BED_ROOT(depth, root, evals, reason) ((void)0)
 #endif
@@ -45,7 +48,11 @@ struct Smem {
     T Q0[NMAX * LD];  // eigenvector blocks (ping)
     T Q1[NMAX * LD];  // eigenvector blocks (pong)
     T M[NMAX * LD];   // load staging, merge matrix, output staging
-    alignas(16) T Vt[NMAX * NMAX];  // reflector k in row k: Vt[k*NMAX + r] = v_k[r]
+    // reflector k in row k: Vt[k*VLD + r] = v_k[r]; the odd row stride keeps
+    // the MFMA operand reads (16 reflectors x 4 rows per instruction) on
+    // distinct banks
+    static constexpr int VLD = NMAX + 1;
+    T Vt[NMAX * VLD];
     T a[NMAX], b[NMAX], tau[NMAX];
     T lam0[NMAX], lam1[NMAX];
     union {
@@ -69,13 +76,16 @@ struct Smem {
             int rlist[NMAX], nrot[NMAX];  // per node: deflated index of each rotation, in scan order
             int col[NMAX];
             int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
-            int ckl[NMAX], ckh[NMAX];  // child block of each row of a merged node
+            int ckl[NMAX], ckh[NMAX];  // child block of each row (its own block for an unmerged leaf)
+            int tklo[NMAX / 16], tkhi[NMAX / 16];  // per 16-row tile: K range of the product
+            int tnlo[NMAX / 16], tnhi[NMAX / 16];  // per 16-row tile: span of its nodes
             int nk[NMAX];
             T nrho[NMAX], nzz[NMAX], nfro[NMAX];
         } m;
         struct {  // back-transform: per block of 16 reflectors, Gram matrix and T factor
-            T gram[((NMAX + 13) / 16) * 256];
-            T tf[((NMAX + 13) / 16) * 256];
+            // 16 x 16 tiles with row stride 17 (bank-conflict free column reads)
+            T gram[((NMAX + 13) / 16) * 272];
+            T tf[((NMAX + 13) / 16) * 272];
         } b;
     } u;
     int bad;
@@ -283,7 +293,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
                             else L = h;
                             ++nmulti;
                         }
-                        if (nmulti < 3 && (U - L) > T(1e-2) * w0) {
+                        if (nmulti < 1 && (U - L) > T(1e-2) * w0) {
                             // Eq. (16): probe toward the origin pole
                             h = (o == jr) ? L + T(0.25) * (U - L) : U - T(0.25) * (U - L);
                             state = 2;
@@ -568,7 +578,7 @@ __device__ __forceinline__ void hh_wave_range(Smem<T, NMAX, NT>& S, const int n,
         }
         if (g0) {
             if (r == k + 1) S.a[k + 1] = xn;
-            S.Vt[(k + 1) * NMAX + r] = vn;
+            S.Vt[(k + 1) * Smem<T, NMAX, NT>::VLD + r] = vn;
             vb[pos_r] = vn;
         }
         // rank-2 update of step k
@@ -724,7 +734,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 S.tau[k] = tauk;
                 S.b[k] = alpha;
             }
-            if (g == 0) S.Vt[k * NMAX + r] = vr;
+            if (g == 0) S.Vt[k * Smem<T, NMAX, NT>::VLD + r] = vr;
             T* vb = S.u.h.vbuf + wave * NMAX;
             if (elem) vb[pos_r] = vr;
             wave_sync();
@@ -849,11 +859,30 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T bet = act ? S.b[s - 1] : T(0);
             const T rho = f_abs(bet);
             const T sgm = (bet < T(0)) ? T(-1) : T(1);
-            if (e < NMAX) {
-                S.u.m.nlo[e] = (e < n) ? nd.lo : e;
-                S.u.m.nhi[e] = (e < n) ? nd.hi : e;
-                S.u.m.ckl[e] = act ? (e < s ? lo : s) : NMAX;
-                S.u.m.ckh[e] = act ? (e < s ? s : hi) : 0;
+            {
+                // Rows of a leaf that is not merged at this depth pass through
+                // the back-multiplication unchanged: their child block is the
+                // leaf itself and M is the identity on it.
+                const bool leaf = (e < n) && !act;
+                const int kl = act ? (e < s ? lo : s) : (leaf ? nd.lo : NMAX);
+                const int kh = act ? (e < s ? s : hi) : (leaf ? nd.hi : 0);
+                if (e < NMAX) {
+                    S.u.m.nlo[e] = (e < n) ? nd.lo : e;
+                    S.u.m.nhi[e] = (e < n) ? nd.hi : e;
+                    S.u.m.ckl[e] = kl;
+                    S.u.m.ckh[e] = kh;
+                }
+                if (leaf)
+                    for (int cc = nd.lo; cc < nd.hi; ++cc) S.M[e * LD + cc] = (cc == e) ? T(1) : T(0);
+                const int tkl = group_min<16>(kl, lane), tkh = group_max<16>(kh, lane);
+                const int tnl = group_min<16>((e < n) ? nd.lo : NMAX, lane);
+                const int tnh = group_max<16>((e < n) ? nd.hi : 0, lane);
+                if ((e & 15) == 0 && e < NMAX) {
+                    S.u.m.tklo[e >> 4] = tkl;
+                    S.u.m.tkhi[e >> 4] = tkh;
+                    S.u.m.tnlo[e >> 4] = tnl;
+                    S.u.m.tnhi[e >> 4] = tnh;
+                }
             }
             if (act) {
                 const T de = Lc[e];
@@ -997,53 +1026,61 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         BED_PHASE(10 + 8 * d + 4);
 
         // ---- M6: back-multiplication Q_next = blockdiag(Q1, Q2) M (Eq. (4)) --
-        // 16x16 MFMA tiles over the block-diagonal band; A = Q_cur restricted
-        // to each row's child block, B = M (zero outside the node blocks).
+        // 16x16 MFMA tiles.  A = Q_cur restricted to each row's child block,
+        // B = M (zero outside the node blocks, the identity on unmerged
+        // leaves), so every computed entry is final: the product of a row and
+        // a column of different nodes is exactly zero, and such entries are
+        // never read.  A wave loads the A operand of its row tile once and
+        // reuses it for every column tile that meets the tile's nodes.
         {
             using MF = Mf<T>;
             constexpr int RT = NMAX / 16;
+            constexpr int KS = NMAX / 4;                    // K steps of four
+            constexpr int CG = (NW >= RT) ? NW / RT : 1;    // column groups per row tile
             const int i16 = lane & 15;
-            for (int tile = wave; tile < RT * RT; tile += NW) {
-                const int r0 = 16 * (tile / RT), c0 = 16 * (tile % RT);
-                if (r0 >= n || c0 >= n) continue;
-                const int r = r0 + i16, c = c0 + i16;
+            BED_MARK(d, 0);
+            for (int idx = wave; idx < RT * CG; idx += NW) {
+                const int rt = idx % RT, cg = idx / RT;
+                const int r0 = 16 * rt;
+                if (r0 >= n) continue;
+                const int klo = S.u.m.tklo[rt], khi = S.u.m.tkhi[rt];
+                const int nlo = S.u.m.tnlo[rt], nhi = S.u.m.tnhi[rt];
+                if (klo >= khi) continue;
+                const int r = r0 + i16;
                 const int ckl = S.u.m.ckl[r], ckh = S.u.m.ckh[r];
-                const int rlo = S.u.m.nlo[r < n ? r : r0], clo = S.u.m.nlo[c < n ? c : c0];
-                const int klo = group_min<16>(ckl, lane), khi = group_max<16>(ckh, lane);
-                const int rmin = group_min<16>(rlo, lane), rmax = group_max<16>(rlo, lane);
-                const int cmin = group_min<16>(clo, lane), cmax = group_max<16>(clo, lane);
-                if (klo >= khi || max(rmin, cmin) > min(rmax, cmax)) continue;
-                typename MF::acc acc = MF::zero();
-                // K in chunks of four MFMA steps; operands of a chunk are
-                // loaded before its MFMAs are issued
-                for (int kb = klo & ~3; kb < khi; kb += 16) {
-                    T av[4], bv[4];
+                const int kb0 = klo & ~3;
+                const int nks = __builtin_amdgcn_readfirstlane((khi - kb0 + 3) >> 2);
+                T av[KS];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int kc = kb + 4 * j;
-                        const int k = (kc < khi) ? kc + (lane >> 4) : 0;
-                        av[j] = (k >= ckl && k < ckh) ? Qc[r * LD + k] : T(0);
-                        bv[j] = S.M[k * LD + c];
+                for (int st = 0; st < KS; ++st) {
+                    const int k = kb0 + 4 * st + (lane >> 4);
+                    av[st] = (st < nks && k >= ckl && k < ckh) ? Qc[r * LD + k] : T(0);
+                }
+                BED_MARK(d, 1);
+                for (int ct = cg; ct < RT; ct += CG) {
+                    const int c0 = 16 * ct;
+                    if (c0 >= n || c0 >= nhi || c0 + 16 <= nlo) continue;
+                    const int c = c0 + i16;
+                    T bv[KS];
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        const int k = kb0 + 4 * st + (lane >> 4);
+                        bv[st] = (st < nks) ? S.M[k * LD + c] : T(0);
                     }
+                    typename MF::acc acc = MF::zero();
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (kb + 4 * j < khi) acc = MF::mma(av[j], bv[j], acc);
-                }
+                    for (int st = 0; st < KS; ++st)
+                        if (st < nks) acc = MF::mma(av[st], bv[st], acc);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = r0 + MF::crow(lane, v);
-                    const int lo = S.u.m.nlo[row], hi = S.u.m.nhi[row];
-                    if (row < n && c < n && hi - lo >= 3 && lo == clo) Qn[row * LD + c] = acc[v];
+                    for (int v = 0; v < 4; ++v) Qn[(r0 + MF::crow(lane, v)) * LD + c] = acc[v];
                 }
             }
-            // nodes not merged at this depth keep their block
+            BED_MARK(d, 2);
+            // eigenvalues of nodes not merged at this depth
             for (int e = t; e < n; e += NT) {
-                const int lo = S.u.m.nlo[e], hi = S.u.m.nhi[e];
-                if (hi - lo < 3) {
-                    for (int cc = lo; cc < hi; ++cc) Qn[e * LD + cc] = Qc[e * LD + cc];
-                    Ln[e] = Lc[e];
-                }
+                if (S.u.m.nhi[e] - S.u.m.nlo[e] < 3) Ln[e] = Lc[e];
             }
+            BED_MARK(d, 3);
         }
         team_sync<NT>();
         BED_PHASE(10 + 8 * d + 5);
@@ -1065,6 +1102,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     {
         using MF = Mf<T>;
         constexpr int RT = NMAX / 16;
+        constexpr int VLD = Smem<T, NMAX, NT>::VLD;
         const int nb = n > 2 ? n - 2 : 0;  // reflectors
         const int NB = (nb + 15) / 16;
         const int i16 = lane & 15;
@@ -1077,12 +1115,12 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) {
                     const int row = 16 * rt + MF::crow(lane, s4);
-                    const T vv = okr ? S.Vt[(k0 + i16) * NMAX + row] : T(0);
+                    const T vv = okr ? S.Vt[(k0 + i16) * VLD + row] : T(0);
                     g = MF::mma(vv, vv, g);
                 }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) S.u.b.gram[bk * 256 + MF::crow(lane, v) * 16 + i16] = g[v];
+            for (int v = 0; v < 4; ++v) S.u.b.gram[bk * 272 + MF::crow(lane, v) * 17 + i16] = g[v];
             wave_sync();
             // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j)
             if (lane < 16) {
@@ -1092,11 +1130,11 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                     const T tj = (k0 + j < nb) ? S.tau[k0 + j] : T(0);
                     T acc = T(0);
 #pragma unroll
-                    for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], S.u.b.gram[bk * 256 + kk * 16 + j], acc);
+                    for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], S.u.b.gram[bk * 272 + kk * 17 + j], acc);
                     trow[j] = (lane < j) ? -tj * acc : (lane == j ? tj : T(0));
                 }
 #pragma unroll
-                for (int j = 0; j < 16; ++j) S.u.b.tf[bk * 256 + lane * 16 + j] = trow[j];
+                for (int j = 0; j < 16; ++j) S.u.b.tf[bk * 272 + lane * 17 + j] = trow[j];
             }
         }
         team_sync<NT>();
@@ -1124,12 +1162,12 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                     for (int s4 = 0; s4 < 4; ++s4) {
                         const int row = 16 * rt + MF::crow(lane, s4);
                         const int kr = k0 + MF::crow(lane, s4);
-                        va[rt][s4] = okr ? S.Vt[(k0 + i16) * NMAX + row] : T(0);
-                        vb[rt][s4] = (kr < nb) ? -S.Vt[kr * NMAX + 16 * rt + i16] : T(0);
+                        va[rt][s4] = okr ? S.Vt[(k0 + i16) * VLD + row] : T(0);
+                        vb[rt][s4] = (kr < nb) ? -S.Vt[kr * VLD + 16 * rt + i16] : T(0);
                     }
                 }
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) tv[s4] = S.u.b.tf[bk * 256 + i16 * 16 + MF::crow(lane, s4)];
+                for (int s4 = 0; s4 < 4; ++s4) tv[s4] = S.u.b.tf[bk * 272 + i16 * 17 + MF::crow(lane, s4)];
                 // X = V_b^T Q (16 x 16 tile of this column block); rows of V_b
                 // above k0 + 1 are zero, so row tiles below bk are skipped
                 typename MF::acc x = MF::zero();
