@@ -202,152 +202,122 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             pv[j] = ok ? dv : FAR;
             z2[j] = ok ? zv * zv : T(0);
         }
-        int o = jr, state = 0, nmulti = 0, nhal = 0;
         T ao = live ? rho * zk[jr] * zk[jr] : T(0);  // rho z_o^2 of the origin pole
         bool done = !live, capped = false;
-        T L = T(0), U = T(0), h = T(0), w0 = T(0), gap = T(0), top = T(0);
-        T dorg = live ? dk[jr] : T(0);
+        T L = T(0), U = T(0), h = T(0), w0 = T(1), gap = T(0), top = T(0);
+        const T dj = live ? dk[jr] : T(0);
+        const bool topr = live && jr == kq - 1;  // the unbounded-above root
+        T dorg = dj;
         if (live) {
-            if (jr < kq - 1) {
-                gap = dk[jr + 1] - dk[jr];
+            if (!topr) {
+                gap = dk[jr + 1] - dj;
                 h = T(0.5) * gap;  // Eq. (13): midpoint of the root's own bracket
                 w0 = gap;
-                state = 1;
             } else {
+                // bracket (0, rho z^T z]; first probe at the Frobenius bound of
+                // Eq. (10)-(11) when it is tighter, else at the midpoint
                 top = rho * S.u.m.nzz[qlo];
-                const T ubf = S.u.m.nfro[qlo] - dk[jr];  // Eq. (10)-(11)
+                const T ubf = S.u.m.nfro[qlo] - dj;
                 w0 = top;
-                if (ubf > T(0) && ubf < top) {
-                    h = ubf;
-                    state = 0;
-                } else {
-                    h = T(0.5) * top;
-                    state = 1;
-                }
+                h = (ubf > T(0) && ubf < top) ? ubf : T(0.5) * top;
             }
         }
 #pragma unroll
         for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
-        int rounds = 0, nev = 0, why = 0;
-        // Progressive removal (Eq. (22)): a converged root's lanes idle; the
-        // wave leaves the loop once all of its roots have stopped.
-        while (__ballot(!done)) {
-            ++rounds;
-            if (!done) {
-                ++nev;
-                // Eq. (8), (18), (21) at h: delta_i = (d_i - d_o) - h
-                T s0 = 0, s1 = 0, s2 = 0, e = 0;
+        int rounds = 0, nev = 0, why = 0, nhal = 0;
+        // Eq. (8), (18), (21) at h: delta_i = (d_i - d_o) - h; returns f, f',
+        // f'' and the stopping bound 8u(1 + rho sum |z_i^2 / delta_i|)
+        auto secular = [&](const T hh, T& f, T& f1, T& f2, T& eb) {
+            T s0 = 0, s1 = 0, s2 = 0, e = 0;
 #pragma unroll
-                for (int j = 0; j < KPL; ++j) {
-                    const T rinv = f_rcp_fast(df[j] - h);
-                    const T t0 = z2[j] * rinv;
-                    const T t1 = t0 * rinv;
-                    s0 += t0;
-                    s1 += t1;
-                    s2 = fma(t1, rinv, s2);
-                    e += f_abs(t0);
-                }
-                s0 = group_sum<LPR>(s0, lane);
-                s1 = group_sum<LPR>(s1, lane);
-                s2 = group_sum<LPR>(s2, lane);
-                e = group_sum<LPR>(e, lane);
-                const T f = T(1) + rho * s0;
-                const T f1 = rho * s1;
-                const T f2 = T(2) * rho * s2;
-                const T eb = T(8) * u * (T(1) + rho * e);
-                if (state == 0) {  // confirm the Frobenius bound
-                    if (f >= T(0)) top = h;
-                    w0 = top;
-                    h = T(0.5) * top;
-                    state = 1;
-                } else if (state == 1 || state == 2) {  // bisection / multi-section
-                    if (f == T(0)) {
-                        done = true;
-                        why = 1;
-                    } else {
-                        if (state == 1) {
-                            if (jr < kq - 1) {
-                                if (f > T(0)) {
-                                    L = T(0);
-                                    U = h;
-                                } else {
-                                    o = jr + 1;  // root nearer d_{j+1}: shift origin
-                                    dorg = dk[jr + 1];
-                                    ao = rho * zk[jr + 1] * zk[jr + 1];
+            for (int j = 0; j < KPL; ++j) {
+                const T rinv = f_rcp_fast(df[j] - hh);
+                const T t0 = z2[j] * rinv;
+                const T t1 = t0 * rinv;
+                s0 += t0;
+                s1 += t1;
+                s2 = fma(t1, rinv, s2);
+                e += f_abs(t0);
+            }
+            s0 = group_sum<LPR>(s0, lane);
+            s1 = group_sum<LPR>(s1, lane);
+            s2 = group_sum<LPR>(s2, lane);
+            e = group_sum<LPR>(e, lane);
+            f = T(1) + rho * s0;
+            f1 = rho * s1;
+            f2 = T(2) * rho * s2;
+            eb = T(8) * u * (T(1) + rho * e);
+        };
+        // Round 1, bisection (Eq. (14)-(15)): the sign of f at the midpoint
+        // picks the nearer pole as origin of tau = lambda - d_origin; the top
+        // root keeps d_k and takes the bracket side by the same sign.
+        {
+            T f, f1, f2, eb;
+            secular(h, f, f1, f2, eb);
+            rounds = 1;
+            nev = live ? 1 : 0;
+            const bool up = f > T(0);
+            const bool shift = live && !topr && !up && f != T(0);
+            if (__ballot(shift)) {
+                const T dnew = shift ? dk[jr + 1] : dorg;
+                const T znew = shift ? zk[jr + 1] : T(0);
+                if (shift) {
+                    ao = rho * znew * znew;
 #pragma unroll
-                                    for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
-                                    L = h - gap;
-                                    U = T(0);
-                                }
-                            } else {
-                                if (f > T(0)) {
-                                    L = T(0);
-                                    U = h;
-                                } else {
-                                    L = h;
-                                    U = top;
-                                }
-                            }
-                        } else {
-                            if (f > T(0)) U = h;
-                            else L = h;
-                            ++nmulti;
-                        }
-                        if (nmulti < 1 && (U - L) > T(1e-2) * w0) {
-                            // Eq. (16): probe toward the origin pole
-                            h = (o == jr) ? L + T(0.25) * (U - L) : U - T(0.25) * (U - L);
-                            state = 2;
-                        } else {
-                            h = T(0.5) * (L + U);
-                            state = 3;
-                        }
-                    }
-                } else {  // Halley, Eq. (20), safeguarded by the bracket
-                    if (f_abs(f) <= eb) {
-                        done = true;
-                        why = 2;
-                    } else {
-                        if (f > T(0)) U = h;
-                        else L = h;
-                        if (U - L <= T(2) * u * (f_abs(L) + f_abs(U))) {
-                            done = true;
-                            why = 3;
-                        } else {
-                            const T den = T(2) * f1 * f1 - f * f2;
-                            T hn = T(0.5) * (L + U);
-                            bool ok = false;
-                            if (den > T(0) && f_finite(den)) {
-                                const T cand = h - T(2) * f * f1 * f_rcp(den);
-                                ok = cand > L && cand < U;
-                                if (ok) hn = cand;
-                            }
-                            if (!ok) {
-                                // Safeguard: root of the one-pole model
-                                // f ~ c - ao/tau through (h, f), ao = rho z_o^2 of
-                                // the origin pole; a plain bisection if it leaves
-                                // the bracket.  Converges where Halley's local
-                                // model fails next to a light origin pole.
-                                const T den2 = fma(f, h, ao);
-                                if (den2 != T(0)) {
-                                    const T cand = ao * h * f_rcp(den2);
-                                    if (cand > L && cand < U) hn = cand;
-                                }
-                            }
-                            if (hn == h) {
-                                done = true;
-                                why = 4;
-                            } else {
-                                h = hn;
-                                if (++nhal >= SEC_CAP) {
-                                    done = true;
-                                    capped = true;
-                                    why = 5;
-                                }
-                            }
-                        }
-                    }
+                    for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dnew;
+                    dorg = dnew;
                 }
             }
+            L = up ? T(0) : (topr ? h : h - gap);
+            U = up ? h : (topr ? top : T(0));
+            // Eq. (16): one multi-section probe toward the origin pole while the
+            // bracket is wide, then Halley from the bracket midpoint
+            const bool probe = (U - L) > T(1e-2) * w0;
+            const T hp = shift ? U - T(0.25) * (U - L) : L + T(0.25) * (U - L);
+            const bool stop = live && f == T(0);
+            why = stop ? 1 : 0;
+            done = done || stop;
+            h = stop ? h : (probe ? hp : T(0.5) * (L + U));
+            nhal = probe ? -1 : 0;  // -1: the next evaluation is the probe
+        }
+        // Progressive removal (Eq. (22)): a converged root's lanes idle; the
+        // wave leaves the loop once all of its roots have stopped.  The body
+        // is select-based: every live root updates its bracket by the sign of
+        // f (Eq. (14)); after the probe the next point is the midpoint, after a
+        // Halley evaluation it is Halley's point if inside the bracket, else
+        // the root of the one-pole model f ~ c - ao/tau through (h, f) (exact
+        // next to a light origin pole), else the midpoint.  A root stops at
+        // f = 0 or |f| <= eb, at a bracket with no interior float, when the
+        // step does not move h, or at the cap.
+        while (__ballot(!done)) {
+            ++rounds;
+            nev += done ? 0 : 1;
+            T f, f1, f2, eb;
+            secular(h, f, f1, f2, eb);
+            const bool hal = nhal >= 0;
+            const bool conv = f == T(0) || (hal && f_abs(f) <= eb);
+            const bool up = f > T(0);
+            const T U2 = up ? h : U;
+            const T L2 = up ? L : h;
+            const bool tight = hal && (U2 - L2) <= T(2) * u * (f_abs(L2) + f_abs(U2));
+            const T den = T(2) * f1 * f1 - f * f2;
+            const T hh = h - T(2) * f * f1 * f_rcp_fast(den);
+            const T hm = ao * h * f_rcp_fast(fma(f, h, ao));
+            const bool okh = den > T(0) && hh > L2 && hh < U2;
+            const bool okm = hm > L2 && hm < U2;
+            const T mid = T(0.5) * (L2 + U2);
+            const T hn = hal ? (okh ? hh : (okm ? hm : mid)) : mid;
+            const bool step = !(conv || tight) && hn != h;
+            const int nh = nhal + 1;
+            const bool cap = step && nh >= SEC_CAP;
+            const bool act = !done;
+            U = act ? U2 : U;
+            L = act ? L2 : L;
+            why = act ? (f == T(0) ? 1 : (conv ? 2 : (tight ? 3 : (!step ? 4 : (cap ? 5 : 0))))) : why;
+            h = (act && step) ? hn : h;
+            nhal = act ? nh : nhal;
+            capped = act ? cap : capped;
+            done = done || !step || cap;
         }
         BED_COUNT(d, rounds);
         if (live && sub == 0) BED_ROOT(d, q, nev, why);
@@ -371,7 +341,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             const bool ok = jj < kq;
             const int js = ok ? jj : 0;
             const T del = (di - S.u.m.rdo[qlo + js]) - S.u.m.rtau[qlo + js];  // d_i - lam_j
-            const T fac = (jj == jr) ? (-del / rho) : (-del / (dk[js] - di));
+            const T fac = -del * f_rcp((jj == jr) ? rho : (dk[js] - di));
             p *= ok ? fac : T(1);
         }
         p = group_prod<LPR>(p, lane);
@@ -473,6 +443,49 @@ __device__ __forceinline__ void roots_vectors_dispatch(Smem<T, NMAX, NT>& S, con
             roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln);
         else
             roots_vectors_dispatch<T, NMAX, NT, KPL * 2>(S, n, d, t, Ln, need);
+    }
+}
+
+// One 16-row tile of the back-multiplication with a K loop of exactly KS
+// steps of four (the caller picks KS >= the tile's K range).  Lane l supplies
+// A[r0 + l%16][k] and B[k][c0 + l%16] for k = kb0 + 4 st + l/16; A entries
+// outside the row's child block are zero and out-of-range rows of B are read
+// at row 0 (finite) against a zero A entry.
+template <typename T, int NMAX, int NT, int KS>
+__device__ __forceinline__ void backmul_rowtile(Smem<T, NMAX, NT>& S, const T* __restrict__ Qc,
+                                                T* __restrict__ Qn, const int n, const int lane,
+                                                const int r0, const int cg, const int CG,
+                                                const int kb0, const int nlo, const int nhi)
+{
+    using MF = Mf<T>;
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int RT = NMAX / 16;
+    const int i16 = lane & 15;
+    const int r = r0 + i16;
+    const int ckl = S.u.m.ckl[r], ckh = S.u.m.ckh[r];
+    T av[KS];
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+        const int k = kb0 + 4 * st + (lane >> 4);
+        const bool ok = k >= ckl && k < ckh;
+        const T a = Qc[r * LD + (ok ? k : 0)];
+        av[st] = ok ? a : T(0);
+    }
+    for (int ct = cg; ct < RT; ct += CG) {
+        const int c0 = 16 * ct;
+        if (c0 >= n || c0 >= nhi || c0 + 16 <= nlo) continue;
+        const int c = c0 + i16;
+        T bv[KS];
+#pragma unroll
+        for (int st = 0; st < KS; ++st) {
+            const int k = kb0 + 4 * st + (lane >> 4);
+            bv[st] = S.M[(k < NMAX ? k : 0) * LD + c];
+        }
+        typename MF::acc acc = MF::zero();
+#pragma unroll
+        for (int st = 0; st < KS; ++st) acc = MF::mma(av[st], bv[st], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Qn[(r0 + MF::crow(lane, v)) * LD + c] = acc[v];
     }
 }
 
@@ -1031,13 +1044,13 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         // leaves), so every computed entry is final: the product of a row and
         // a column of different nodes is exactly zero, and such entries are
         // never read.  A wave loads the A operand of its row tile once and
-        // reuses it for every column tile that meets the tile's nodes.
+        // reuses it for every column tile that meets the tile's nodes.  The
+        // K loop has a fixed length (4, 8 or 16 steps, chosen once per row
+        // tile) and operands come from clamped addresses, so the tile has no
+        // per-step branches.
         {
-            using MF = Mf<T>;
             constexpr int RT = NMAX / 16;
-            constexpr int KS = NMAX / 4;                    // K steps of four
             constexpr int CG = (NW >= RT) ? NW / RT : 1;    // column groups per row tile
-            const int i16 = lane & 15;
             BED_MARK(d, 0);
             for (int idx = wave; idx < RT * CG; idx += NW) {
                 const int rt = idx % RT, cg = idx / RT;
@@ -1045,35 +1058,18 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 if (r0 >= n) continue;
                 const int klo = S.u.m.tklo[rt], khi = S.u.m.tkhi[rt];
                 const int nlo = S.u.m.tnlo[rt], nhi = S.u.m.tnhi[rt];
+                BED_MARK(d, 4);
                 if (klo >= khi) continue;
-                const int r = r0 + i16;
-                const int ckl = S.u.m.ckl[r], ckh = S.u.m.ckh[r];
                 const int kb0 = klo & ~3;
                 const int nks = __builtin_amdgcn_readfirstlane((khi - kb0 + 3) >> 2);
-                T av[KS];
-#pragma unroll
-                for (int st = 0; st < KS; ++st) {
-                    const int k = kb0 + 4 * st + (lane >> 4);
-                    av[st] = (st < nks && k >= ckl && k < ckh) ? Qc[r * LD + k] : T(0);
-                }
-                BED_MARK(d, 1);
-                for (int ct = cg; ct < RT; ct += CG) {
-                    const int c0 = 16 * ct;
-                    if (c0 >= n || c0 >= nhi || c0 + 16 <= nlo) continue;
-                    const int c = c0 + i16;
-                    T bv[KS];
-#pragma unroll
-                    for (int st = 0; st < KS; ++st) {
-                        const int k = kb0 + 4 * st + (lane >> 4);
-                        bv[st] = (st < nks) ? S.M[k * LD + c] : T(0);
-                    }
-                    typename MF::acc acc = MF::zero();
-#pragma unroll
-                    for (int st = 0; st < KS; ++st)
-                        if (st < nks) acc = MF::mma(av[st], bv[st], acc);
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Qn[(r0 + MF::crow(lane, v)) * LD + c] = acc[v];
-                }
+                BED_MARK(d, 5);
+                if (nks <= 4)
+                    backmul_rowtile<T, NMAX, NT, 4>(S, Qc, Qn, n, lane, r0, cg, CG, kb0, nlo, nhi);
+                else if (nks <= 8)
+                    backmul_rowtile<T, NMAX, NT, 8>(S, Qc, Qn, n, lane, r0, cg, CG, kb0, nlo, nhi);
+                else
+                    backmul_rowtile<T, NMAX, NT, NMAX / 4>(S, Qc, Qn, n, lane, r0, cg, CG, kb0, nlo,
+                                                           nhi);
             }
             BED_MARK(d, 2);
             // eigenvalues of nodes not merged at this depth
