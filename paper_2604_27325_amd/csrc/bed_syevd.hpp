@@ -88,7 +88,7 @@ struct Smem {
             T tf[((NMAX + 13) / 16) * 272];
         } b;
     } u;
-    int bad;
+    int badw[NW];
     int capped;
     int anyrot;
 };
@@ -147,6 +147,33 @@ __device__ __forceinline__ int count_below(const T* x, int len, T v, bool inclus
         else hi = mid;
     }
     return lo;
+}
+
+// The same count by binary lifting with power-of-two steps STEP, STEP/2, ..., 1
+// (STEP a compile-time bound >= half of the longest list): a fixed chain of
+// loads from clamped addresses and selects, with no branch.
+template <int STEP, typename T>
+__device__ __forceinline__ int count_lift(const T* x, int len, T v, bool inclusive, int base)
+{
+    const int probe = base + STEP;
+    const int idx = (probe <= len ? probe : len) - 1;
+    const T xv = x[idx > 0 ? idx : 0];
+    const bool below = inclusive ? (xv <= v) : (xv < v);
+    base = (probe <= len && below) ? probe : base;
+    if constexpr (STEP > 1) return count_lift<STEP / 2>(x, len, v, inclusive, base);
+    else return base;
+}
+template <int NMAX, typename T>
+__device__ __forceinline__ int count_below_steps(const T* x, int len, T v, bool inclusive,
+                                                 int step)
+{
+    // step is wave-uniform: one branch selects the unrolled chain
+    if (step >= 32 && NMAX >= 64) return count_lift<32>(x, len, v, inclusive, 0);
+    if (step >= 16 && NMAX >= 32) return count_lift<16>(x, len, v, inclusive, 0);
+    if (step >= 8) return count_lift<8>(x, len, v, inclusive, 0);
+    if (step >= 4) return count_lift<4>(x, len, v, inclusive, 0);
+    if (step >= 2) return count_lift<2>(x, len, v, inclusive, 0);
+    return count_lift<1>(x, len, v, inclusive, 0);
 }
 
 // Uniform index into a register array without dynamic VGPR indexing: a
@@ -664,28 +691,47 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
 
     BED_PHASE(0);
     // ------------------------------------------------------------ load
-    if (t == 0) {
-        S.bad = 0;
-        S.capped = 0;
-    }
-    team_sync<NT>();
+    // 16-byte loads when the rows allow it (n a multiple of the vector width
+    // and A 16-byte aligned), else one element per thread and step.  A
+    // non-finite entry of the lower triangle is flagged per wave by a ballot.
     {
+        constexpr int VW = 16 / sizeof(T);
         bool bad = false;
-        for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
-            T v = Ain[e];
-            if (j <= i && !f_finite(v)) bad = true;  // lower triangle only
-            S.M[i * LD + j] = v;
-            j += NT % n;
-            i += NT / n;
-            if (j >= n) {
-                j -= n;
-                ++i;
+        if (n % VW == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0) {
+            typedef T vec_t __attribute__((ext_vector_type(VW)));
+            const vec_t* Av = reinterpret_cast<const vec_t*>(Ain);
+            const int nv = n * n / VW;
+            for (int e = t; e < nv; e += NT) {
+                const vec_t v = Av[e];
+                const int i = (e * VW) / n, j = (e * VW) % n;
+#pragma unroll
+                for (int q = 0; q < VW; ++q) {
+                    if (j + q <= i && !f_finite(v[q])) bad = true;
+                    S.M[i * LD + j + q] = v[q];
+                }
+            }
+        } else {
+            for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+                T v = Ain[e];
+                if (j <= i && !f_finite(v)) bad = true;  // lower triangle only
+                S.M[i * LD + j] = v;
+                j += NT % n;
+                i += NT / n;
+                if (j >= n) {
+                    j -= n;
+                    ++i;
+                }
             }
         }
-        if (bad) atomicOr(&S.bad, 1);
+        const bool wbad = __ballot(bad) != 0;
+        if (lane == 0) S.badw[wave] = wbad ? 1 : 0;
+        if (t == 0) S.capped = 0;
     }
     team_sync<NT>();
-    if (S.bad) {
+    int anybad = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) anybad |= S.badw[w];
+    if (anybad) {
         if (Q_out)
             for (int e = t; e < n * n; e += NT) Q_out[e] = f_nan<T>();
         for (int e = t; e < n; e += NT) lam_out[e] = f_nan<T>();
@@ -863,15 +909,13 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
 
     // ------------------------------------------------------------ merges
     for (int d = D - 1; d >= 0; --d) {
-        // ---- M1 (wave 0): z, sort, deflation, compaction -------------------
-        if (wave == 0) {
+        // ---- M1: node structure (data-independent) on the last wave while
+        // wave 0 forms z, sorts, deflates and compacts --------------------------
+        if (wave == NW - 1) {
             const int e = lane;
             const Node nd = node_of(e < n ? e : 0, d, n);
             const bool act = (e < n) && (nd.hi - nd.lo >= 3);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
-            const T bet = act ? S.b[s - 1] : T(0);
-            const T rho = f_abs(bet);
-            const T sgm = (bet < T(0)) ? T(-1) : T(1);
             {
                 // Rows of a leaf that is not merged at this depth pass through
                 // the back-multiplication unchanged: their child block is the
@@ -897,16 +941,36 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                     S.u.m.tnhi[e >> 4] = tnh;
                 }
             }
+        }
+        if (wave == 0) {
+            const int e = lane;
+            const Node nd = node_of(e < n ? e : 0, d, n);
+            BED_MARK(d, 8);
+            const bool act = (e < n) && (nd.hi - nd.lo >= 3);
+            const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
+            const T bet = act ? S.b[s - 1] : T(0);
+            const T rho = f_abs(bet);
+            const T sgm = (bet < T(0)) ? T(-1) : T(1);
+            BED_MARK(d, 9);
+            // largest power of two <= the largest child size at this depth
+            const int cmax = (((n + (1 << d) - 1) >> d) + 1) >> 1;
+            const int sstep = 1 << (31 - __builtin_clz(cmax > 0 ? cmax : 1));
             if (act) {
                 const T de = Lc[e];
                 const T ze = (e < s) ? sgm * Qc[(s - 1) * LD + e] : Qc[s * LD + e];
-                const int pos = (e < s) ? (e - lo) + count_below(Lc + s, hi - s, de, false)
-                                        : (e - s) + count_below(Lc + lo, s - lo, de, true);
+                // rank among the sibling's sorted values (one chain per lane:
+                // left elements count right ones strictly below, right
+                // elements count left ones below or equal -- a stable merge)
+                const bool left = e < s;
+                const int pos = (left ? e - lo : e - s) +
+                                count_below_steps<NMAX>(Lc + (left ? s : lo), left ? hi - s : s - lo,
+                                                        de, !left, sstep);
                 S.u.m.sd[lo + pos] = de;
                 S.u.m.sz[lo + pos] = ze;
                 S.u.m.sperm[lo + pos] = e;
             }
             wave_sync();
+            BED_MARK(d, 10);
             T dp = act ? S.u.m.sd[e] : T(0);
             T zp = act ? S.u.m.sz[e] : T(0);
             // node sums over [lo, hi) from wave prefix sums: z^T z, d^T (z o z),
@@ -919,6 +983,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T dz = __shfl(pdz, ihi) - (lo > 0 ? __shfl(pdz, ilo) : T(0));
             const T d2 = __shfl(pd2, ihi) - (lo > 0 ? __shfl(pd2, ilo) : T(0));
             const T dmax = act ? f_max(f_abs(S.u.m.sd[lo]), f_abs(S.u.m.sd[hi - 1])) : T(0);
+            BED_MARK(d, 11);
             const T tol = T(8) * u * f_max(dmax, rho * zz0);
             // Frobenius norm of the node (Eq. (10)), from D + rho z z^T
             const T fro2 = d2 + T(2) * rho * dz + rho * rho * zz0 * zz0;
@@ -931,11 +996,13 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T zpr = __shfl(zp, prev), dpr = __shfl(dp, prev);
             bool cand = false;
             if (act && !defl && prev != e) {
-                const T rr = f_hypot(zpr, zp);
-                const T c = zp / rr, sn = zpr / rr;
-                cand = f_abs((dp - dpr) * c * sn) <= tol;
+                // |z| >= tol/rho here (no under/overflow in the squares); the
+                // sequential scan below recomputes passing pairs exactly
+                const T ir = f_rcp(f_sqrt(fma(zpr, zpr, zp * zp)));
+                cand = f_abs((dp - dpr) * (zp * ir) * (zpr * ir)) <= tol;
             }
             const uint64_t cmask = __ballot(cand);
+            BED_MARK(d, 12);
             if (act) {
                 S.u.m.rpart[e] = -1;
                 S.u.m.sdefl[e] = defl ? 1 : 0;
@@ -1001,6 +1068,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 hasrot = (cmask & lane_range(lo, hi)) != 0;
             }
             const uint64_t live2 = __ballot(act && !defl);
+            BED_MARK(d, 13);
             const uint64_t dead = __ballot(act && defl);
             const int k = __popcll(live2 & lane_range(lo, hi));
             if (act) {
@@ -1017,6 +1085,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 }
             }
             const T pzz = wave_prefix_sum((act && !defl) ? zp * zp : T(0));
+            BED_MARK(d, 14);
             const T zz = __shfl(pzz, ihi) - (lo > 0 ? __shfl(pzz, ilo) : T(0));
             if (act && e == lo) {
                 S.u.m.nk[lo] = k;
@@ -1027,6 +1096,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             }
             const bool anyrot = __ballot(hasrot) != 0;
             if (e == 0) S.anyrot = anyrot ? 1 : 0;
+            BED_MARK(d, 15);
         }
         team_sync<NT>();
         BED_PHASE(10 + 8 * d + 0);
