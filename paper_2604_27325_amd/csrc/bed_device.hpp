@@ -48,6 +48,13 @@ __device__ __forceinline__ double f_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float f_rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double f_rcp_fast(double x) { return 1.0 / x; }
 __device__ __forceinline__ float f_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// 1/sqrt(x): hardware estimate plus one Newton step (FP32); exact in FP64
+__device__ __forceinline__ float f_rsqrt(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    return y * fmaf(-0.5f * x * y, y, 1.5f);
+}
+__device__ __forceinline__ double f_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float f_div(float a, float b) { return a * f_rcp(b); }
 __device__ __forceinline__ double f_div(double a, double b) { return a / b; }

@@ -38,6 +38,15 @@
 
 namespace bed {
 
+// Waves that run the Householder reduction of a team: the row block of a
+// wave (NMAX^2/(64 HW) registers per lane) must fit the register budget.
+#ifndef BED_HH_WAVES
+#define BED_HH_WAVES(T, NMAX, NT) ((NMAX) == 64 ? ((NT) / 64 < 4 ? (NT) / 64 : 4) : 1)
+#endif
+template <typename T, int NMAX, int NT> struct HH_WAVES {
+    static constexpr int value = BED_HH_WAVES(T, NMAX, NT);
+};
+
 constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
 
 template <typename T, int NMAX, int NT>
@@ -117,9 +126,17 @@ __device__ __forceinline__ void leaf2(T p, T q, T r, T lam[2], T Q[4])
 {
     T c = T(1), s = T(0), t = T(0);
     if (q != T(0)) {
-        T th = (r - p) / (T(2) * q);
-        t = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
-        c = T(1) / f_hypot(T(1), t);
+        if constexpr (sizeof(T) == 4) {
+            // hardware reciprocal (rcp(inf) = 0: a huge |th| gives t = 0, the
+            // rotation's limit) and square root; c^2 + s^2 = 1 to a few ulps
+            const T th = (r - p) * f_rcp_fast(T(2) * q);
+            t = (th < T(0) ? T(-1) : T(1)) * f_rcp_fast(f_abs(th) + f_sqrt(fma(th, th, T(1))));
+            c = f_rcp_fast(f_sqrt(fma(t, t, T(1))));
+        } else {
+            const T th = (r - p) / (T(2) * q);
+            t = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
+            c = T(1) / f_hypot(T(1), t);
+        }
         s = t * c;
     }
     T l1 = p - t * q, l2 = r + t * q;
@@ -516,17 +533,24 @@ __device__ __forceinline__ void backmul_rowtile(Smem<T, NMAX, NT>& S, const T* _
     }
 }
 
-// Householder tridiagonalization by one wave (FP32).  Lane (r, g), g < G =
-// 64/NMAX, keeps row r of the columns c = g + G j, j < CPT, in registers; p = A v
-// is a per-lane dot product plus a butterfly over the G column groups, so a
-// step needs no barrier and no cross-wave exchange.  Steps whose dead columns
-// (c <= k, where v_c = 0) fill the first Q0 chunks of four registers run in the
-// instance for that Q0, whose chunk range is a compile-time constant.
+// Householder tridiagonalization (Sec. 2; textbook, Golub-Van Loan 8.3) on HW
+// waves of the team.  Lane (r, g) keeps row r of the columns c = g + G j,
+// j < CPT, in registers, with G = HW * 64/NMAX column groups (64/NMAX groups
+// per wave, each holding all rows): a cyclic split, so every group shrinks at
+// the rate of the trailing matrix.  Within a wave p = A v is a per-lane dot
+// product plus a butterfly over its groups; across waves one barrier per step
+// exchanges the partial products together with the owner's pre-update pivot
+// column k+1 (a look-ahead of one column), after which every wave forms w, the
+// next pivot column and the next reflector on its own.  v and w reach a
+// wave's groups through its own LDS copies (group-major: column c at
+// (c % G) CPT + c / G), one 16-byte read per chunk of four columns.
 //
-// Software pipeline: step k forms the updated pivot column k+1 and its norm
-// directly, then the reflector of step k+1 (alpha, tau, v, its LDS broadcast)
-// and only after that issues its own rank-2 update, so the dependent scalar
-// chain and the reductions of step k+1 overlap the update's FMAs.
+// Steps whose dead columns (c <= k, where v_c = 0) fill a wave's first Q0
+// chunks run in that wave's instance for Q0, whose chunk range is a
+// compile-time constant.  Software pipeline: step k forms the updated pivot
+// column and its norm first, then the reflector of step k+1 and its LDS
+// broadcast, and issues its own rank-2 update last, so the scalar chain and
+// the reductions overlap the update's FMAs.
 template <typename T>
 struct HhRefl {
     T alpha, tau, rv0;
@@ -534,36 +558,44 @@ struct HhRefl {
 template <typename T>
 __device__ __forceinline__ HhRefl<T> hh_reflector(const T x0, const T sig)
 {
-    // alpha = -sgn(x0) ||x||, v = (1, x_2.. / (x0 - alpha)), tau = 2 / (v^T v) of
-    // the v actually formed; tau = 0 when the sub-column is already zero
+    // alpha = -sgn(x0) mu, mu = ||x||; v = (1, x_2.. / (x0 - alpha)) with
+    // x0 - alpha = sgn(x0)(|x0| + mu); tau = (mu + |x0|)/mu = 2/(v^T v) in
+    // exact arithmetic.  Two independent reciprocals (1/mu, 1/(|x0| + mu)).
+    // tau = 0 when the sub-column is already zero.
     const bool z = (sig == T(0));
-    const T mu = f_sqrt(x0 * x0 + sig);
+    const T s2 = fma(x0, x0, sig);
+    const T rmu = f_rsqrt(s2);
+    const T mu = s2 * rmu;
+    const T ax = f_abs(x0);
+    const T sg = (x0 < T(0)) ? T(-1) : T(1);
     HhRefl<T> h;
-    h.alpha = z ? x0 : ((x0 < T(0)) ? mu : -mu);
-    const T rv = f_rcp(x0 - h.alpha);
-    h.rv0 = z ? T(1) : rv;
-    const T tv = T(2) * f_rcp(T(1) + sig * h.rv0 * h.rv0);
-    h.tau = z ? T(0) : tv;
+    h.alpha = z ? x0 : -sg * mu;
+    h.rv0 = z ? T(1) : sg * f_rcp(ax + mu);
+    h.tau = z ? T(0) : fma(ax, rmu, T(1));
     return h;
 }
 
-template <typename T, int NMAX, int NT, int Q0>
-__device__ __forceinline__ void hh_wave_range(Smem<T, NMAX, NT>& S, const int n, const int lane,
-                                              T (&ar)[NMAX * NMAX / 64], T& xr, T& sig, T& vr,
-                                              T& tauk)
+template <typename T, int NMAX, int NT, int HW, int Q0>
+__device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, const int lane,
+                                         const int wave, T (&ar)[NMAX * NMAX / (64 * HW)], T& xr,
+                                         T& sig, T& vr, T& tauk)
 {
-    constexpr int G = 64 / NMAX;
+    constexpr int GW = 64 / NMAX;   // column groups per wave
+    constexpr int G = HW * GW;      // column groups of the team
     constexpr int CPT = NMAX / G;
     constexpr int NCH = CPT / 4;
-    const int r = lane % NMAX, g = lane / NMAX;
-    const bool g0 = lane < NMAX;
+    const int r = lane % NMAX, gl = lane / NMAX, g = wave * GW + gl;
+    const int glast = wave * GW + GW - 1;  // last group of this wave
+    const bool g0 = gl == 0;
     const int pos_r = (r % G) * CPT + r / G;
-    T* vb = S.u.h.vbuf;
-    T* wb = S.u.h.wbuf;
-    const int kb = (Q0 == 0) ? 0 : 4 * G * Q0 - 1;
-    const int ke = min(4 * G * (Q0 + 1) - 1, n - 2);
-    // loop invariant: vr, tauk and the LDS copy of v belong to step k; ar holds
-    // the matrix after steps < k
+    T* vb = S.u.h.vbuf + wave * NMAX;
+    T* wb = S.u.h.wbuf + wave * NMAX;
+    // instance Q0 = NCH: every column of this wave is dead, but the wave
+    // keeps stepping (barriers, pivot column, next reflector) until n - 2
+    const int kb = (Q0 == 0) ? 0 : glast + G * (4 * Q0 - 1);
+    const int ke = (Q0 == NCH) ? n - 2 : min(glast + G * (4 * Q0 + 3), n - 2);
+    // loop invariant: vr, tauk and this wave's LDS copy of v belong to step
+    // k; ar holds the matrix after steps < k
     for (int k = kb; k < ke; ++k) {
         wave_sync();
         T vc[CPT];
@@ -578,47 +610,62 @@ __device__ __forceinline__ void hh_wave_range(Smem<T, NMAX, NT>& S, const int n,
             pp1 = fma(ar[4 * q + 3], vc[4 * q + 3], pp1);
         }
         T pr = pp0 + pp1;
-        if constexpr (G >= 4) pr += xmove<16>(pr, lane);
-        if constexpr (G >= 2) pr += xmove<32>(pr, lane);
+        if constexpr (GW >= 4) pr += xmove<16>(pr, lane);
+        if constexpr (GW >= 2) pr += xmove<32>(pr, lane);
+        // pivot column k + 1 before this step's update, from its owner group;
+        // in this instance its register index lies in [4 Q0, 4 Q0 + 4)
+        const int c1 = k + 1;
+        const int g1 = c1 % G;
+        T a1 = T(0);  // valid in group g1 (never this wave in instance NCH)
+        if constexpr (Q0 < NCH) a1 = pick<4>(ar + 4 * Q0, (c1 / G) & 3);
+        T cb;
+        if constexpr (HW > 1) {
+            T* pa = S.u.h.part + (k & 1) * HW * NMAX;
+            if (g0) pa[wave * NMAX + r] = pr;
+            if (g == g1) S.u.h.colb[(k & 1) * NMAX + r] = a1;
+            team_sync<NT>();
+            pr = T(0);
+#pragma unroll
+            for (int w2 = 0; w2 < HW; ++w2) pr += pa[w2 * NMAX + r];
+            cb = S.u.h.colb[(k & 1) * NMAX + r];
+        } else {
+            cb = a1;
+            if constexpr (GW == 2) {
+                const T o32 = xmove<32>(a1, lane);
+                cb = (g == g1) ? a1 : o32;
+            } else if constexpr (GW == 4) {
+                const T o16 = xmove<16>(a1, lane);
+                const T o32 = xmove<32>(a1, lane);
+                const T o48 = xmove<32>(o16, lane);
+                const int dd = g ^ g1;
+                cb = dd == 0 ? a1 : (dd == 1 ? o16 : (dd == 2 ? o32 : o48));
+            }
+        }
         pr *= tauk;
         const T pv = wave_total(g0 ? pr * vr : T(0));
         const T wr = pr - T(0.5) * tauk * pv * vr;
         if (g0) wb[pos_r] = wr;
+        // v and w at column k + 1 are the values of row k + 1
+        const T v1 = bcast(vr, k + 1), w1 = bcast(wr, k + 1);
         wave_sync();
         T wc[CPT];
 #pragma unroll
         for (int j = 4 * Q0; j < CPT; ++j) wc[j] = wb[g * CPT + j];
-        // pivot column k + 1 after this step, from its owner group
-        const int c1 = k + 1;
-        const int g1 = c1 % G;
-        const int pos1 = g1 * CPT + c1 / G;
-        const T v1 = vb[pos1], w1 = wb[pos1];
-        // in this instance c1 / G lies in [4 Q0, 4 Q0 + 4)
-        const T a1 = pick<4>(ar + 4 * Q0, (c1 / G) & 3);
-        const T xo = fma(-wr, v1, fma(-vr, w1, a1));  // valid in group g1
-        T xn = xo;
-        if constexpr (G == 2) {
-            const T o32 = xmove<32>(xo, lane);
-            xn = (g == g1) ? xo : o32;
-        } else if constexpr (G == 4) {
-            const T o16 = xmove<16>(xo, lane);
-            const T o32 = xmove<32>(xo, lane);
-            const T o48 = xmove<32>(o16, lane);
-            const int dd = g ^ g1;
-            xn = dd == 0 ? xo : (dd == 1 ? o16 : (dd == 2 ? o32 : o48));
-        }
+        const T xn = fma(-wr, v1, fma(-vr, w1, cb));  // pivot column k + 1, row r
         const T sn = wave_total((g0 && r > k + 2) ? xn * xn : T(0));
         // reflector of step k + 1 (harmless past the last step: nothing reads
         // reflector n - 2, and b[n - 2], a[n - 2] are rewritten afterwards)
         const HhRefl<T> h = hh_reflector(bcast(xn, k + 2), sn);
         const T vn = (r == k + 2) ? T(1) : ((r > k + 2 && sn != T(0)) ? xn * h.rv0 : T(0));
-        if (lane == 0) {
+        if (wave == 0 && lane == 0) {
             S.tau[k + 1] = h.tau;
             S.b[k + 1] = h.alpha;
         }
         if (g0) {
-            if (r == k + 1) S.a[k + 1] = xn;
-            S.Vt[(k + 1) * Smem<T, NMAX, NT>::VLD + r] = vn;
+            if (wave == 0) {
+                if (r == k + 1) S.a[k + 1] = xn;
+                S.Vt[(k + 1) * Smem<T, NMAX, NT>::VLD + r] = vn;
+            }
             vb[pos_r] = vn;
         }
         // rank-2 update of step k
@@ -629,18 +676,27 @@ __device__ __forceinline__ void hh_wave_range(Smem<T, NMAX, NT>& S, const int n,
         vr = vn;
         tauk = h.tau;
     }
-    if constexpr (Q0 + 1 < NCH) hh_wave_range<T, NMAX, NT, Q0 + 1>(S, n, lane, ar, xr, sig, vr, tauk);
+    if constexpr (Q0 < NCH)
+        hh_range<T, NMAX, NT, HW, Q0 + 1>(S, n, lane, wave, ar, xr, sig, vr, tauk);
 }
 
-template <typename T, int NMAX, int NT>
-__device__ __forceinline__ void householder_wave(Smem<T, NMAX, NT>& S, const int n, const int lane)
+template <typename T, int NMAX, int NT, int HW>
+__device__ __forceinline__ void householder(Smem<T, NMAX, NT>& S, const int n, const int lane,
+                                            const int wave)
 {
     constexpr int LD = Smem<T, NMAX, NT>::LD;
-    constexpr int G = 64 / NMAX;
+    constexpr int GW = 64 / NMAX;
+    constexpr int G = HW * GW;
     constexpr int CPT = NMAX / G;
     static_assert(CPT % 4 == 0, "chunks of four columns");
-    const int r = lane % NMAX, g = lane / NMAX;
-    const bool g0 = lane < NMAX;
+    if (wave >= HW) {
+        // waves outside the reduction only keep the barrier count
+        if constexpr (HW > 1)
+            for (int k = 0; k < n - 2; ++k) team_sync<NT>();
+        return;
+    }
+    const int r = lane % NMAX, gl = lane / NMAX, g = wave * GW + gl;
+    const bool g0 = gl == 0;
     T ar[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
@@ -653,18 +709,20 @@ __device__ __forceinline__ void householder_wave(Smem<T, NMAX, NT>& S, const int
     const HhRefl<T> h = hh_reflector(bcast(xr, 1), sig);
     T vr = (r == 1) ? T(1) : ((r > 1 && sig != T(0)) ? xr * h.rv0 : T(0));
     T tauk = h.tau;
-    if (lane == 0) {
+    if (wave == 0 && lane == 0) {
         S.tau[0] = h.tau;
         S.b[0] = h.alpha;
     }
     if (g0) {
-        if (r == 0) S.a[0] = xr;
-        S.Vt[r] = vr;
-        S.u.h.vbuf[(r % G) * CPT + r / G] = vr;
+        if (wave == 0) {
+            if (r == 0) S.a[0] = xr;
+            S.Vt[r] = vr;
+        }
+        S.u.h.vbuf[wave * NMAX + (r % G) * CPT + r / G] = vr;
     }
-    hh_wave_range<T, NMAX, NT, 0>(S, n, lane, ar, xr, sig, vr, tauk);
+    hh_range<T, NMAX, NT, HW, 0>(S, n, lane, wave, ar, xr, sig, vr, tauk);
     wave_sync();
-    if (g0 && n >= 2) {
+    if (wave == 0 && g0 && n >= 2) {
         if (r == n - 2) S.a[n - 2] = xr;
         if (r == n - 1) S.b[n - 2] = xr;
     }
@@ -741,118 +799,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     BED_PHASE(1);
 
     // ------------------------------------------------------------ Householder
-    // FP32 teams of up to four waves reduce on one wave (its row block fits
-    // the register budget of two resident teams per SIMD); otherwise the team
-    // shares the columns.
-    if constexpr (sizeof(T) == 4 && NT <= 256) {
-        if (wave == 0) householder_wave<T, NMAX, NT>(S, n, lane);
-    } else
-    // Thread (r, g) keeps row r of the columns c = g + G j (j < CPT) in
-    // registers: a cyclic split, so every column group shrinks at the same
-    // rate as the trailing matrix does and whole chunks of dead columns
-    // (c <= k, where v_c = 0) are skipped by wave-uniform branches.  Each step
-    // k uses one team barrier: the partial products of p = A v and the
-    // pre-update pivot column k+1 cross waves together; every wave then forms
-    // w and the next pivot column on its own (a look-ahead of one column).
-    // v and w reach the column groups through per-wave LDS vectors stored
-    // group-major (column c at (c % G) CPT + c / G), one 16-byte read per chunk.
-    {
-        static_assert(CPT % 4 == 0, "Householder chunks of four columns");
-        constexpr int NCH = CPT / 4;
-        constexpr int GPW = 64 / NMAX < 1 ? 1 : 64 / NMAX;  // column groups per wave
-        typedef T colvec __attribute__((ext_vector_type(CPT)));
-        colvec ar;
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) {
-            const int c = g + G * j;
-            ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
-        }
-        const int g_last = wave * GPW + GPW - 1;  // last column group of this wave
-        T xr = (r < n) ? S.M[r * LD] : T(0);     // pivot column 0 (lower triangle)
-        const bool elem = lane < NMAX;
-        const int pos_r = (r % G) * CPT + r / G;  // group-major slot of index r
-        for (int k = 0; k + 2 < n; ++k) {
-            if (t == k) S.a[k] = xr;
-            const T x0 = bcast(xr, k + 1);
-            const T sig = wave_sum((elem && r > k + 1) ? xr * xr : T(0), lane);
-            T alpha, tauk, rv0;
-            if (sig == T(0)) {
-                alpha = x0;
-                tauk = T(0);
-                rv0 = T(1);
-            } else {
-                const T mu = f_sqrt(x0 * x0 + sig);
-                alpha = (x0 < T(0)) ? mu : -mu;
-                rv0 = f_rcp(x0 - alpha);
-                // tau = 2 / (v^T v) of the v actually formed (v_0 = 1, v_i = x_i rv0),
-                // so each reflector is orthogonal to rounding whatever rv0's error
-                tauk = T(2) * f_rcp(T(1) + sig * rv0 * rv0);
-            }
-            const T vr = (r == k + 1) ? T(1) : ((r > k + 1 && sig != T(0)) ? xr * rv0 : T(0));
-            if (t == 0) {
-                S.tau[k] = tauk;
-                S.b[k] = alpha;
-            }
-            if (g == 0) S.Vt[k * Smem<T, NMAX, NT>::VLD + r] = vr;
-            T* vb = S.u.h.vbuf + wave * NMAX;
-            if (elem) vb[pos_r] = vr;
-            wave_sync();
-            const int c1 = k + 1;
-            const int pos1 = (c1 % G) * CPT + c1 / G;
-            const T v1 = vb[pos1];
-            // all reads issued before any use: one LDS wait, not one per chunk
-            T vc[CPT];
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) vc[j] = vb[g * CPT + j];
-            T pp0 = T(0), pp1 = T(0);
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) {
-                if (g_last + G * (4 * q + 3) > k) {  // chunk has a live column
-                    pp0 = fma(ar[4 * q + 0], vc[4 * q + 0], pp0);
-                    pp1 = fma(ar[4 * q + 1], vc[4 * q + 1], pp1);
-                    pp0 = fma(ar[4 * q + 2], vc[4 * q + 2], pp0);
-                    pp1 = fma(ar[4 * q + 3], vc[4 * q + 3], pp1);
-                }
-            }
-            T* pa = S.u.h.part + (k & 1) * G * NMAX;
-            pa[g * NMAX + r] = pp0 + pp1;
-            if (g == c1 % G) S.u.h.colb[(k & 1) * NMAX + r] = ar[c1 / G];
-            team_sync<NT>();
-            const T cb = S.u.h.colb[(k & 1) * NMAX + r];
-            T pr = T(0);
-#pragma unroll
-            for (int gg = 0; gg < G; ++gg) pr += pa[gg * NMAX + r];
-            pr *= tauk;
-            const T pv = wave_sum(elem ? pr * vr : T(0), lane);
-            const T wr = pr - T(0.5) * tauk * pv * vr;
-            T* wb = S.u.h.wbuf + wave * NMAX;
-            if (elem) wb[pos_r] = wr;
-            wave_sync();
-            T wc[CPT];
-#pragma unroll
-            for (int j = 0; j < CPT; ++j) wc[j] = wb[g * CPT + j];
-            const T w1 = wb[pos1];
-#pragma unroll
-            for (int q = 0; q < NCH; ++q) {
-                if (g_last + G * (4 * q + 3) > k) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int j = 4 * q + i;
-                        ar[j] = fma(-wr, vc[j], fma(-vr, wc[j], ar[j]));
-                    }
-                }
-            }
-            xr = fma(-wr, v1, fma(-vr, w1, cb));
-        }
-        if (n >= 2) {
-            if (t == n - 2) S.a[n - 2] = xr;
-            if (t == n - 1) S.b[n - 2] = xr;
-        }
-        {
-            const int c1 = n - 1;
-            if (g == c1 % G && r == c1) S.a[n - 1] = ar[c1 / G];
-        }
-    }
+    householder<T, NMAX, NT, HH_WAVES<T, NMAX, NT>::value>(S, n, lane, wave);
     team_sync<NT>();
     // The staging buffer becomes the merge matrix M: clear it so that entries
     // outside every node block (never written by a merge) are zero -- the MFMA
@@ -873,20 +820,19 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         T ae = (e < n) ? S.a[e] : T(0);
         // Eq. (3): every split s of a node with >= 3 elements subtracts |b_{s-1}|
         // from a_{s-1} and a_s (ancestors first).
-        for (int d = 0; d < D; ++d) {
-            if (e < n) {
-                Node nd = node_of(e, d, n);
-                if (nd.hi - nd.lo >= 3 && (e == nd.s - 1 || e == nd.s)) ae -= f_abs(S.b[nd.s - 1]);
-            }
-        }
+        // (branch-free: every depth's coupling is read from a clamped address
+        // and applied by a select; the leaf is the first node of size <= 2)
         int llo = e, lhi = e + 1;
-        if (e < n) {
-            for (int d = 0; d <= D; ++d) {
-                Node nd = node_of(e, d, n);
-                llo = nd.lo;
-                lhi = nd.hi;
-                if (lhi - llo <= 2) break;
-            }
+        bool found = false;
+        for (int d = 0; d <= D; ++d) {
+            const Node nd = node_of(e < n ? e : 0, d, n);
+            const bool split = d < D && nd.hi - nd.lo >= 3 && (e == nd.s - 1 || e == nd.s);
+            const T bs = S.b[nd.s >= 1 ? nd.s - 1 : 0];
+            ae -= (e < n && split) ? f_abs(bs) : T(0);
+            const bool leaf = !found && nd.hi - nd.lo <= 2;
+            llo = leaf ? nd.lo : llo;
+            lhi = leaf ? nd.hi : lhi;
+            found = found || leaf;
         }
         if (e < n) S.a[e] = ae;  // torn diagonal
         wave_sync();
