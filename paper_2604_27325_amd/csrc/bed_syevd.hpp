@@ -79,11 +79,10 @@ struct Smem {
             int itrow[NMAX];          // child-order row of deflated item at [lo + k, hi)
             T itv[NMAX];              // item values: roots at [lo, lo+k), deflated after
             T rtau[NMAX], rdo[NMAX];  // root offset and its origin pole value
-            T zh[NMAX], rnrm[NMAX];
+            T zh[NMAX];
             T rc[NMAX], rs[NMAX];
             int rpart[NMAX];
             int rlist[NMAX], nrot[NMAX];  // per node: deflated index of each rotation, in scan order
-            int col[NMAX];
             int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
             int ckl[NMAX], ckh[NMAX];  // child block of each row (its own block for an unmerged leaf)
             int tklo[NMAX / 16], tkhi[NMAX / 16];  // per 16-row tile: K range of the product
@@ -394,24 +393,13 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     team_sync<NT>();
     BED_PHASE(10 + 8 * d + 2);
 
-    // ---- M4: eigenvector norms (Eq. (24)) and output order -------------------
-    if (qact && jr < kq) {
-        const T dorg = S.u.m.rdo[q];
-        const T tj = S.u.m.rtau[q];
-        T s2 = T(0);
-#pragma unroll
-        for (int j = 0; j < KPL; ++j) {
-            const int ii = sub + LPR * j;
-            const bool ok = ii < kq;
-            const int is = ok ? ii : 0;
-            const T w = S.u.m.zh[qlo + is] * f_rcp((dk[is] - dorg) - tj);
-            s2 += ok ? w * w : T(0);
-        }
-        s2 = group_sum<LPR>(s2, lane);
-        if (sub == 0) S.u.m.rnrm[q] = f_rcp(f_sqrt(s2));
-    }
-    // rank of item jr among the node's m items (roots, then deflated)
+    // ---- M4: output order, eigenvector norms (Eq. (24)) and the merge matrix
+    // M = P G (U (+) I) with rows in child order, in one pass per root: the
+    // lanes of root j form w_i = zhat_i / (d_i - lambda_j), reduce |w|^2, and
+    // write -w_i / ||w|| into column rank(j).  Slots outside the node go to
+    // the padding column NMAX of M, which no product reads (no branches).
     if (qact) {
+        // rank of item jr among the node's m items (roots, then deflated)
         const T my = S.u.m.itv[q];
         int cnt = 0;
 #pragma unroll
@@ -422,41 +410,45 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             cnt += (ok && (ov < my || (ov == my && vv < jr))) ? 1 : 0;
         }
         cnt = group_sum<LPR>(cnt, lane);
-        if (sub == 0) {
-            S.u.m.col[q] = qlo + cnt;
-            Ln[qlo + cnt] = my;
-        }
-    }
-    team_sync<NT>();
-    BED_PHASE(10 + 8 * d + 3);
-
-    // ---- M5: merge matrix M = P G (U (+) I), rows in child order -------------
-    if (qact) {
-        const int c = S.u.m.col[q];
+        const int c = qlo + cnt;
+        if (sub == 0) Ln[c] = my;
         if (jr < kq) {
             const T dorg = S.u.m.rdo[q];
             const T tj = S.u.m.rtau[q];
-            const T nr = S.u.m.rnrm[q];
+            T wv[KPL];
+            T s2 = T(0);
 #pragma unroll
             for (int j = 0; j < KPL; ++j) {
                 const int ii = sub + LPR * j;
-                if (ii < kq) {
-                    const T del = (dk[ii] - dorg) - tj;  // d_i - lam_j
-                    S.M[S.u.m.ndrow[qlo + ii] * LD + c] = -S.u.m.zh[qlo + ii] * nr * f_rcp(del);
-                } else if (ii < mq) {
-                    S.M[S.u.m.itrow[qlo + ii] * LD + c] = T(0);
-                }
+                const bool ok = ii < kq;
+                const int is = ok ? ii : 0;
+                const T w = S.u.m.zh[qlo + is] * f_rcp((dk[is] - dorg) - tj);
+                wv[j] = w;
+                s2 += ok ? w * w : T(0);
+            }
+            s2 = group_sum<LPR>(s2, lane);
+            const T nr = f_rcp(f_sqrt(s2));
+#pragma unroll
+            for (int j = 0; j < KPL; ++j) {
+                const int ii = sub + LPR * j;
+                const bool nd = ii < kq, df = !nd && ii < mq;
+                const int is = (nd || df) ? ii : 0;
+                const int rn = S.u.m.ndrow[qlo + is], rd = S.u.m.itrow[qlo + is];
+                const int row = nd ? rn : (df ? rd : 0);  // row 0 for unused slots
+                S.M[row * LD + ((nd || df) ? c : NMAX)] = nd ? -wv[j] * nr : T(0);
             }
         } else {
             const int myrow = S.u.m.itrow[q];
 #pragma unroll
             for (int j = 0; j < KPL; ++j) {
                 const int row = qlo + sub + LPR * j;
-                if (row < qlo + mq) S.M[row * LD + c] = (row == myrow) ? T(1) : T(0);
+                const bool in = row < qlo + mq;
+                S.M[(in ? row : qlo) * LD + (in ? c : NMAX)] = (row == myrow) ? T(1) : T(0);
             }
         }
     }
     team_sync<NT>();
+    BED_PHASE(10 + 8 * d + 3);
     if (S.anyrot) {
         // Type-2 rotations act on the rows of M in reverse scan order.
         if (qact && sub == 0) {
