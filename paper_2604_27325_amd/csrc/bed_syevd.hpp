@@ -1110,23 +1110,33 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         const int nb = n > 2 ? n - 2 : 0;  // reflectors
         const int NB = (nb + 15) / 16;
         const int i16 = lane & 15;
-        // Gram matrices G_b = V_b^T V_b (one wave per block)
+        BED_MARK(7, 0);
+        // Gram matrices G_b = V_b^T V_b (one wave per block); one MFMA chain
+        // per row tile, summed at the end (independent chains overlap)
         for (int bk = wave; bk < NB; bk += NW) {
             const int k0 = 16 * bk;
-            typename MF::acc g = MF::zero();
             const bool okr = k0 + i16 < nb;
-            for (int rt = bk; rt < RT; ++rt) {
+            typename MF::acc g = MF::zero();
+            typename MF::acc gt[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+                gt[rt] = MF::zero();
+                if (rt < bk) continue;  // rows above the block's first reflector are zero
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) {
                     const int row = 16 * rt + MF::crow(lane, s4);
                     const T vv = okr ? S.Vt[(k0 + i16) * VLD + row] : T(0);
-                    g = MF::mma(vv, vv, g);
+                    gt[rt] = MF::mma(vv, vv, gt[rt]);
                 }
             }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                if (rt >= bk) g += gt[rt];
 #pragma unroll
             for (int v = 0; v < 4; ++v) S.u.b.gram[bk * 272 + MF::crow(lane, v) * 17 + i16] = g[v];
             wave_sync();
             // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j)
+            BED_MARK(7, 1);
             if (lane < 16) {
                 T trow[16];
 #pragma unroll
@@ -1141,10 +1151,13 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 for (int j = 0; j < 16; ++j) S.u.b.tf[bk * 272 + lane * 17 + j] = trow[j];
             }
         }
+        BED_MARK(7, 2);
         team_sync<NT>();
+        constexpr int NBMAX = (NMAX + 13) / 16;  // blocks for n = NMAX
         for (int ct = wave; ct < RT; ct += NW) {
             const int c0 = 16 * ct;
             if (c0 >= n) continue;
+            BED_MARK(7, 3);
             const int c = c0 + i16;
             typename MF::acc q[RT];
 #pragma unroll
@@ -1155,10 +1168,15 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                     q[rt][v] = (row < n && c < n) ? Qc[row * LD + c] : T(0);
                 }
             }
-            for (int bk = NB - 1; bk >= 0; --bk) {
+            // blocks last to first, unrolled so that the zero row tiles of
+            // each V_b (below its first reflector) are skipped at compile time
+#pragma unroll
+            for (int bi = 0; bi < NBMAX; ++bi) {
+                const int bk = NBMAX - 1 - bi;
+                if (bk >= NB) continue;
                 const int k0 = 16 * bk;
                 const bool okr = k0 + i16 < nb;
-                // operands of this block, loaded before the MFMA chain
+                // operands of this block, loaded before the MFMA chains
                 T va[RT][4], vb[RT][4], tv[4];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
@@ -1172,27 +1190,33 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 }
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) tv[s4] = S.u.b.tf[bk * 272 + i16 * 17 + MF::crow(lane, s4)];
-                // X = V_b^T Q (16 x 16 tile of this column block); rows of V_b
-                // above k0 + 1 are zero, so row tiles below bk are skipped
-                typename MF::acc x = MF::zero();
+                // X = V_b^T Q (16 x 16 tile of this column block): one chain
+                // per row tile at or below the block, then summed
+                typename MF::acc xt[RT];
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
+                    xt[rt] = MF::zero();
                     if (rt < bk) continue;
 #pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) x = MF::mma(va[rt][s4], q[rt][s4], x);
+                    for (int s4 = 0; s4 < 4; ++s4) xt[rt] = MF::mma(va[rt][s4], q[rt][s4], xt[rt]);
                 }
+                typename MF::acc x = xt[RT - 1];
+#pragma unroll
+                for (int rt = 0; rt < RT - 1; ++rt)
+                    if (rt >= bk) x += xt[rt];
                 // Y = T_b X
                 typename MF::acc y = MF::zero();
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) y = MF::mma(tv[s4], x[s4], y);
-                // Q -= V_b Y
+                // Q -= V_b Y, the row tiles' chains interleaved
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    if (rt < bk) continue;
+                for (int s4 = 0; s4 < 4; ++s4) {
 #pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) q[rt] = MF::mma(vb[rt][s4], y[s4], q[rt]);
+                    for (int rt = 0; rt < RT; ++rt)
+                        if (rt >= bk) q[rt] = MF::mma(vb[rt][s4], y[s4], q[rt]);
                 }
             }
+            BED_MARK(7, 4);
             // sign canonicalization: largest |.| entry positive, lowest row on ties
             T best = T(-1), bval = T(0);
             int brow = 1 << 20;
