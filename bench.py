@@ -33,6 +33,16 @@ PEAK_FP32_TFLOPS = 157.3
 BATCH = 512
 
 
+def nmax_of(n):
+    """Size class of the solver's team for order n."""
+    return 16 if n <= 16 else (32 if n <= 32 else 64)
+
+
+def threads_of(n):
+    """Threads per matrix of the default schedule for order n."""
+    return {16: 64, 32: 128, 64: 512}[nmax_of(n)]
+
+
 def merge_tree(n):
     """(m, m1, m2) of every merge of the dyadic tearing tree of size n."""
     merges = []
@@ -428,7 +438,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": profiled_traffic(f"k_syevd_uniform_f32_n{n}_b{BATCH}"),
-                     "kernel": f"k_syevd_uniform<float, {n}, 256>",
+                     "kernel": f"k_syevd_uniform<float, {nmax_of(n)}, {threads_of(n)}>",
                      "flops_per_launch": BATCH * F, "kernel_ms": ev},
         "cpu_baseline": cpu,
         "per_n": per_n,

@@ -88,14 +88,14 @@ TeamShape class_shape(int cls, const bed_tune &t)
     switch (cls) {
     case 0: return TeamShape{16, 64};
     case 1: return TeamShape{32, t.threads_mid > 0 ? t.threads_mid : 128};
-    default: return TeamShape{64, t.threads_big > 0 ? t.threads_big : 256};
+    default: return TeamShape{64, t.threads_big > 0 ? t.threads_big : 512};
     }
 }
 
 bed_tune default_tune()
 {
     bed_tune t;
-    t.threads_big = 256;
+    t.threads_big = 512;
     t.threads_mid = 128;
     t.waves_per_cu = 0;
     t.order = 0;

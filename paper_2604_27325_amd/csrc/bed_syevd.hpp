@@ -47,6 +47,18 @@ template <typename T, int NMAX, int NT> struct HH_WAVES {
     static constexpr int value = BED_HH_WAVES(T, NMAX, NT);
 };
 
+// Waves that form Q_H = H_0 H_1 ... H_{n-3} explicitly while the others reduce
+// (0: the back-transform applies the reflectors in compact-WY form instead).
+// Each holds NMAX/AW >= 16 rows of Q_H, at most 32 values per lane.
+template <typename T, int NMAX, int NT> struct QH_WAVES {
+    static constexpr int spare = NT / 64 - HH_WAVES<T, NMAX, NT>::value;
+    static constexpr int p = (spare >= 4 && NMAX >= 64) ? 4 : ((spare >= 2 && NMAX >= 32) ? 2 : (spare >= 1 ? 1 : 0));
+    static constexpr int value = (p > 0 && NMAX * NMAX / (64 * p) <= 32) ? p : 0;
+};
+// With a single reducing wave there is no barrier per step; the team meets
+// after every QH_SYNC steps so that the accumulating waves can follow.
+constexpr int QH_SYNC = 4;
+
 constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
 
 template <typename T, int NMAX, int NT>
@@ -57,11 +69,12 @@ struct Smem {
     T Q0[NMAX * LD];  // eigenvector blocks (ping)
     T Q1[NMAX * LD];  // eigenvector blocks (pong)
     T M[NMAX * LD];   // load staging, merge matrix, output staging
-    // reflector k in row k: Vt[k*VLD + r] = v_k[r]; the odd row stride keeps
-    // the MFMA operand reads (16 reflectors x 4 rows per instruction) on
-    // distinct banks
-    static constexpr int VLD = NMAX + 1;
-    T Vt[NMAX * VLD];
+    // reflector k in row k: Vt[k*VLD + r] = v_k[r].  Compact WY: the odd row
+    // stride keeps the MFMA operand reads (16 reflectors x 4 rows per
+    // instruction) on distinct banks.  Explicit Q_H: 16-byte aligned rows for
+    // vector reads; the buffer holds Q_H (row-major) once the reduction ends.
+    static constexpr int VLD = QH_WAVES<T, NMAX, NT>::value ? NMAX + 4 : NMAX + 1;
+    alignas(16) T Vt[NMAX * VLD];
     T a[NMAX], b[NMAX], tau[NMAX];
     T lam0[NMAX], lam1[NMAX];
     union {
@@ -667,26 +680,108 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
         sig = sn;
         vr = vn;
         tauk = h.tau;
+        if constexpr (HW == 1 && QH_WAVES<T, NMAX, NT>::value > 0)
+            if (k % QH_SYNC == QH_SYNC - 1) team_sync<NT>();
     }
     if constexpr (Q0 < NCH)
         hh_range<T, NMAX, NT, HW, Q0 + 1>(S, n, lane, wave, ar, xr, sig, vr, tauk);
 }
 
+// Explicit Q_H = H_0 H_1 ... H_{n-3} on the AW waves that do not reduce:
+// Q_H <- Q_H (I - tau_k v_k v_k^T) = Q_H - tau_k (Q_H v_k) v_k^T for k = 0, 1,
+// ..., once reflector k (row k of Vt, tau[k]) has passed a team barrier.
+// Wave aw holds rows [aw RW, aw RW + RW) of Q_H; lane (rl, cg) holds row
+// aw RW + rl, columns [cg VPL, cg VPL + VPL).
+template <typename T, int NMAX, int NT>
+struct QhShape {
+    static constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
+    static constexpr int RW = AW ? NMAX / AW : NMAX;  // rows per wave
+    static constexpr int VPL = AW ? NMAX * RW / 64 : 1;  // values per lane
+};
+template <typename T, int NMAX, int NT>
+__device__ __forceinline__ void qh_apply(const Smem<T, NMAX, NT>& S, const int lane, const int k,
+                                         T (&qh)[QhShape<T, NMAX, NT>::VPL])
+{
+    constexpr int RW = QhShape<T, NMAX, NT>::RW;
+    constexpr int VPL = QhShape<T, NMAX, NT>::VPL;
+    constexpr int VLD = Smem<T, NMAX, NT>::VLD;
+    constexpr int VW = 16 / sizeof(T);
+    static_assert(RW >= 16 && VPL % VW == 0 && VLD % VW == 0, "explicit Q_H layout");
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    const int cg = lane / RW;
+    const vec_t* vp = reinterpret_cast<const vec_t*>(S.Vt + k * VLD + cg * VPL);
+    T v[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL / VW; ++q) {
+        const vec_t x = vp[q];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) v[q * VW + e] = x[e];
+    }
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int i = 0; i < VPL; i += 2) {
+        s0 = fma(qh[i], v[i], s0);
+        s1 = fma(qh[i + 1], v[i + 1], s1);
+    }
+    T s = s0 + s1;  // (Q_H v_k) at this row: sum over the column groups
+    if constexpr (RW <= 16) s += xmove<16>(s, lane);
+    if constexpr (RW <= 32) s += xmove<32>(s, lane);
+    const T ts = S.tau[k] * s;
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) qh[i] = fma(-ts, v[i], qh[i]);
+}
+
+// Barrier schedule of the reduction: one barrier at the start of every step
+// with several reducing waves; with one, a barrier after every QH_SYNC-th step
+// when Q_H is accumulated, else none.  Every wave of the team follows it.
+template <int HW, int AW>
+__device__ __forceinline__ bool hh_barrier_at(const int k)
+{
+    return HW > 1 || (AW > 0 && k % QH_SYNC == QH_SYNC - 1);
+}
+
 template <typename T, int NMAX, int NT, int HW>
-__device__ __forceinline__ void householder(Smem<T, NMAX, NT>& S, const int n, const int lane,
-                                            const int wave)
+__device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, const int lane,
+                                           const int wave, const bool want_q,
+                                           T (&qh)[QhShape<T, NMAX, NT>::VPL])
 {
     constexpr int LD = Smem<T, NMAX, NT>::LD;
     constexpr int GW = 64 / NMAX;
     constexpr int G = HW * GW;
     constexpr int CPT = NMAX / G;
+    constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
     static_assert(CPT % 4 == 0, "chunks of four columns");
     if (wave >= HW) {
+        if constexpr (AW > 0) {
+            if (wave < HW + AW) {
+                // returns the first reflector not yet applied (the rest follow
+                // the barrier that closes the reduction)
+                constexpr int RW = QhShape<T, NMAX, NT>::RW;
+                constexpr int VPL = QhShape<T, NMAX, NT>::VPL;
+                const int row = (wave - HW) * RW + lane % RW, c0 = (lane / RW) * VPL;
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) qh[i] = (row == c0 + i) ? T(1) : T(0);
+                int j = 0;
+                for (int k = 0; k < n - 2; ++k) {
+                    if (!hh_barrier_at<HW, AW>(k)) continue;
+                    team_sync<NT>();
+                    // visible: reflectors up to k (barrier before step k) or up
+                    // to k + 1 (barrier after step k)
+                    const int jl = min(HW > 1 ? k : k + 1, n - 3);
+                    for (; j <= jl; ++j)
+                        if (want_q) qh_apply<T, NMAX, NT>(S, lane, j, qh);
+                }
+                return j;
+            }
+        }
         // waves outside the reduction only keep the barrier count
-        if constexpr (HW > 1)
-            for (int k = 0; k < n - 2; ++k) team_sync<NT>();
-        return;
+        for (int k = 0; k < n - 2; ++k)
+            if (hh_barrier_at<HW, AW>(k)) team_sync<NT>();
+        return 0;
     }
+    // The reduction is one dependent chain; its waves issue ahead of the
+    // accumulating waves that share their SIMDs.
+    if constexpr (AW > 0) __builtin_amdgcn_s_setprio(1);
     const int r = lane % NMAX, gl = lane / NMAX, g = wave * GW + gl;
     const bool g0 = gl == 0;
     T ar[CPT];
@@ -719,6 +814,8 @@ __device__ __forceinline__ void householder(Smem<T, NMAX, NT>& S, const int n, c
         if (r == n - 1) S.b[n - 2] = xr;
     }
     if (g == (n - 1) % G && r == n - 1) S.a[n - 1] = pick<CPT>(ar, (n - 1) / G);
+    if constexpr (AW > 0) __builtin_amdgcn_s_setprio(0);
+    return 0;
 }
 
 template <typename T, int NMAX, int NT>
@@ -791,13 +888,41 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     BED_PHASE(1);
 
     // ------------------------------------------------------------ Householder
-    householder<T, NMAX, NT, HH_WAVES<T, NMAX, NT>::value>(S, n, lane, wave);
+    constexpr int HW = HH_WAVES<T, NMAX, NT>::value;
+    constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
+    const bool qh_wave = AW > 0 && wave >= HW && wave < HW + AW && Q_out != nullptr;
+    T qh[QhShape<T, NMAX, NT>::VPL];
+    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr, qh);
     team_sync<NT>();
+    if constexpr (AW > 0) {
+        // reflectors written after the last barrier of the reduction
+        if (qh_wave)
+            for (; qj < n - 2; ++qj) qh_apply<T, NMAX, NT>(S, lane, qj, qh);
+    }
     // The staging buffer becomes the merge matrix M: clear it so that entries
     // outside every node block (never written by a merge) are zero -- the MFMA
     // back-multiplication reads them against zero A entries.
     for (int e = t; e < NMAX * LD; e += NT) S.M[e] = T(0);
     team_sync<NT>();
+    if constexpr (AW > 0) {
+        // every reflector has been read: Q_H replaces them
+        if (qh_wave) {
+            constexpr int RW = QhShape<T, NMAX, NT>::RW;
+            constexpr int VPL = QhShape<T, NMAX, NT>::VPL;
+            constexpr int VLD = Smem<T, NMAX, NT>::VLD;
+            constexpr int VW = 16 / sizeof(T);
+            typedef T vec_t __attribute__((ext_vector_type(VW)));
+            const int row = (wave - HW) * RW + lane % RW, c0 = (lane / RW) * VPL;
+            vec_t* qp = reinterpret_cast<vec_t*>(S.Vt + row * VLD + c0);
+#pragma unroll
+            for (int q = 0; q < VPL / VW; ++q) {
+                vec_t x;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) x[e] = qh[q * VW + e];
+                qp[q] = x;
+            }
+        }
+    }
     BED_PHASE(2);
 
     // ------------------------------------------------------------ tear + leaves
@@ -1099,6 +1224,108 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     }
 
     // ------------------------------------------------------------ back-transform
+    if constexpr (AW > 0) {
+        // Q_A = Q_H Q_T on 16x16x4 MFMA tiles: wave w computes row tiles
+        // [p RPW, p RPW + RPW) of column tile w % CT (p = w / CT).  Lane group kk
+        // covers k in [kk KS, kk KS + KS), so each lane reads a contiguous
+        // slice of its Q_H row.  The product goes to Qn unsigned; each wave
+        // leaves, per column, its entry of largest magnitude (lowest row on
+        // ties) for the sign rule applied by the store.
+        using MF = Mf<T>;
+        constexpr int CT = NMAX / 16;
+        constexpr int RT = NMAX / 16;
+        static_assert(NW >= CT, "one wave per column tile at least");
+        constexpr int WPC = (NW / CT > RT) ? RT : NW / CT;  // waves per column tile
+        constexpr int RPW = RT / WPC;
+        constexpr int KS = NMAX / 4;
+        constexpr int VLD = Smem<T, NMAX, NT>::VLD;
+        constexpr int VW = 16 / sizeof(T);
+        static_assert(WPC * NMAX <= int(sizeof(S.u.b.gram) / sizeof(T)), "sign candidates");
+        typedef T vec_t __attribute__((ext_vector_type(VW)));
+        const int i16 = lane & 15, kk = lane >> 4;
+        if (wave < CT * WPC) {
+            const int ct = wave % CT, part = wave / CT;
+            const int c = 16 * ct + i16;
+            T bq[KS];
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int k = kk * KS + s4;
+                bq[s4] = (k < n) ? Qc[k * LD + c] : T(0);
+            }
+            typename MF::acc q[RPW];
+#pragma unroll
+            for (int pr = 0; pr < RPW; ++pr) {
+                const int rt = part * RPW + pr;
+                const vec_t* ap = reinterpret_cast<const vec_t*>(S.Vt + (16 * rt + i16) * VLD + kk * KS);
+                T a[KS];
+#pragma unroll
+                for (int q4 = 0; q4 < KS / VW; ++q4) {
+                    const vec_t x = ap[q4];
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) a[q4 * VW + e] = x[e];
+                }
+                q[pr] = MF::zero();
+#pragma unroll
+                for (int s4 = 0; s4 < KS; ++s4) q[pr] = MF::mma(a[s4], bq[s4], q[pr]);
+            }
+            T best = T(-1), bval = T(0);
+            int brow = 1 << 20;
+#pragma unroll
+            for (int pr = 0; pr < RPW; ++pr) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * (part * RPW + pr) + MF::crow(lane, v);
+                    const T av = f_abs(q[pr][v]);
+                    const bool take = row < n && (av > best || (av == best && row < brow));
+                    best = take ? av : best;
+                    brow = take ? row : brow;
+                    bval = take ? q[pr][v] : bval;
+                    if (row < n && c < n) Qn[row * LD + c] = q[pr][v];
+                }
+            }
+            {
+                const T ob = xmove<16>(best, lane);
+                const int orow = xmove<16>(brow, lane);
+                const T oval = xmove<16>(bval, lane);
+                const bool take = ob > best || (ob == best && orow < brow);
+                best = take ? ob : best;
+                brow = take ? orow : brow;
+                bval = take ? oval : bval;
+            }
+            {
+                const T ob = xmove<32>(best, lane);
+                const int orow = xmove<32>(brow, lane);
+                const T oval = xmove<32>(bval, lane);
+                const bool take = ob > best || (ob == best && orow < brow);
+                bval = take ? oval : bval;
+            }
+            if (kk == 0) S.u.b.gram[part * NMAX + c] = bval;
+        }
+        team_sync<NT>();
+        BED_PHASE(4);
+        // parts in increasing row order: a later part wins only when strictly
+        // larger in magnitude
+        for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+            T bv = S.u.b.gram[j];
+#pragma unroll
+            for (int pp = 1; pp < WPC; ++pp) {
+                const T o = S.u.b.gram[pp * NMAX + j];
+                bv = (f_abs(o) > f_abs(bv)) ? o : bv;
+            }
+            const T x = Qn[i * LD + j];
+            Q_out[e] = (bv < T(0)) ? -x : x;
+            j += NT % n;
+            i += NT / n;
+            if (j >= n) {
+                j -= n;
+                ++i;
+            }
+        }
+        for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+        if (t == 0 && info_out) *info_out = S.capped;
+        BED_PHASE(5);
+        return;
+    } else {
     // Q_A = H_0 H_1 ... H_{n-3} Q_T in compact-WY blocks of 16 reflectors,
     // H_{16b} ... H_{16b+15} = I - V_b T_b V_b^T (T_b upper triangular), applied
     // for b = last .. 0.  Each wave keeps whole 16-column tiles of Q in MFMA
@@ -1278,6 +1505,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
     if (t == 0 && info_out) *info_out = S.capped;
     BED_PHASE(5);
+    }
 }
 
 }  // namespace bed

@@ -121,3 +121,35 @@ def test_plan_create_refused_during_capture(uneven):
         with torch.cuda.graph(g):
             bed.Plan(torch.float32, [3, 5, 7])
     assert ei.value.status == 5  # BED_ERR_CAPTURE
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+@pytest.mark.parametrize("big,mid", [(64, 64), (128, 128), (256, 64), (512, 128)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
+    """Every team shape (threads per matrix of the n > 32 and 16 < n <= 32
+    classes), including those that accumulate Q_H explicitly on the waves
+    outside the reduction, at every n from 1 to 64."""
+    rng = np.random.default_rng(3100 + big + mid)
+    ns = list(range(1, 65)) + [64, 63, 48, 33, 32, 31, 17, 16, 3]
+    mats = [workloads.gaussian_sym(rng, 1, n)[0] for n in ns]
+    mats += [workloads.covariance(rng, 1, n)[0] for n in (64, 40, 32, 20)]
+    ns += [64, 40, 32, 20]
+    _, flat = workloads.pack(mats)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    flat = flat.astype(npdt)
+    plan = bed.Plan(dtype, ns, tune={"threads_big": big, "threads_mid": mid,
+                                     "persistent": persistent})
+    print(f"[shape dtype={dtype} big={big} mid={mid} persistent={persistent}]", flush=True)
+    A = torch.from_numpy(flat).to(DEV)
+    lam = torch.empty(int(np.sum(ns)), dtype=dtype, device=DEV)
+    Q = torch.empty_like(A)
+    info = torch.empty(len(ns), dtype=torch.int32, device=DEV)
+    plan.run(A, lam, Q, info)
+    torch.cuda.synchronize()
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    lg, qg = split(ns, lam.cpu().numpy(), Q.cpu().numpy())
+    lo, qo = split(ns, lam_o, Q_o)
+    worst, fails = compare_batch(mats, lg, qg, lo, qo, npdt, info=info.cpu().numpy())
+    print(f"  worst {worst}", flush=True)
+    assert not fails, fails[:3]
