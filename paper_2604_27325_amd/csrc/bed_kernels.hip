@@ -60,8 +60,12 @@ k_syevd_persist(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
         __syncthreads();
         if (it >= count) break;
         const WorkItem w = items[it];
+        // opaque thread index: per-thread addresses are formed anew for each
+        // matrix instead of being held (and spilled) across the loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
-                                info ? info + w.idx : nullptr, S, threadIdx.x);
+                                info ? info + w.idx : nullptr, S, tid);
     }
     if (threadIdx.x == 0) {
         __threadfence();

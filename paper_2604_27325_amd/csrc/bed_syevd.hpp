@@ -219,28 +219,24 @@ __device__ __forceinline__ T pick(const T* a, int idx)
     }
 }
 
-// Merge phases M2-M5 of one depth with KPL poles (or items) per lane held in
-// registers: secular roots, Loewner zhat, eigenvector norms and output order,
-// merge-matrix assembly (incl. type-2 rotations).  All team threads call it.
-template <typename T, int NMAX, int NT, int KPL>
-__device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n, const int d,
-                                              const int t, T* __restrict__ Ln)
+// M2 of one depth: secular roots (Sec. 2.3.1-2.3.4) with SL lanes per root and
+// KPL poles per lane in registers.  Threads [0, NMAX SL) take part (whole
+// waves); the per-root bracket and Halley logic runs on every lane of a root,
+// so fewer lanes per root cost less issue time than they add in sums.
+template <typename T, int NMAX, int NT, int SL, int KPL>
+__device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n, const int d,
+                                              const int t)
 {
-    constexpr int LD = Smem<T, NMAX, NT>::LD;
-    constexpr int LPR = NT / NMAX;
+    constexpr int LPR = SL;
     const int lane = t & 63;
     const T u = fp<T>::u;
     // absent poles: a far, finite pole with zero weight (its terms vanish and
     // its reciprocal stays a normal number)
     const T FAR = sizeof(T) == 4 ? T(1e30f) : T(1e300);
-    (void)lane;
-
-    // ---- M2: secular roots (Sec. 2.3.1-2.3.4), LPR lanes per root ---------
     const int q = t / LPR, sub = t % LPR;
     const Node qn = node_of(q < n ? q : 0, d, n);
     const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
     const int qlo = qn.lo;
-    const int mq = qn.hi - qn.lo;
     const int kq = qact ? S.u.m.nk[qlo] : 0;
     const int jr = q - qlo;
     const T* dk = S.u.m.dk + qlo;
@@ -249,13 +245,15 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     {
         const bool live = qact && jr < kq;
         // this lane's share of the poles: i = sub + LPR*j
-        T pv[KPL], z2[KPL], df[KPL];
+        // df = pole - origin pole; the poles themselves are read again from
+        // LDS if the origin moves
+        T z2[KPL], df[KPL];
 #pragma unroll
         for (int j = 0; j < KPL; ++j) {
             const int i = sub + LPR * j;
             const bool ok = live && i < kq;
             const T dv = dk[ok ? i : 0], zv = zk[ok ? i : 0];
-            pv[j] = ok ? dv : FAR;
+            df[j] = ok ? dv : FAR;
             z2[j] = ok ? zv * zv : T(0);
         }
         T ao = live ? rho * zk[jr] * zk[jr] : T(0);  // rho z_o^2 of the origin pole
@@ -279,7 +277,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             }
         }
 #pragma unroll
-        for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dorg;
+        for (int j = 0; j < KPL; ++j) df[j] = df[j] - dorg;
         int rounds = 0, nev = 0, why = 0, nhal = 0;
         // Eq. (8), (18), (21) at h: delta_i = (d_i - d_o) - h; returns f, f',
         // f'' and the stopping bound 8u(1 + rho sum |z_i^2 / delta_i|)
@@ -320,7 +318,11 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
                 if (shift) {
                     ao = rho * znew * znew;
 #pragma unroll
-                    for (int j = 0; j < KPL; ++j) df[j] = pv[j] - dnew;
+                    for (int j = 0; j < KPL; ++j) {
+                        const int i = sub + LPR * j;
+                        const bool ok = i < kq;  // shift implies live
+                        df[j] = (ok ? dk[ok ? i : 0] : FAR) - dnew;
+                    }
                     dorg = dnew;
                 }
             }
@@ -383,6 +385,40 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
             S.u.m.itv[q] = dorg + h;
             if (capped) atomicAdd(&S.capped, 1);
         }
+    }
+}
+
+// Merge phases M2-M5 of one depth with KPL poles (or items) per lane held in
+// registers: secular roots, Loewner zhat, eigenvector norms and output order,
+// merge-matrix assembly (incl. type-2 rotations).  All team threads call it.
+template <typename T, int NMAX, int NT, int KPL>
+__device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n, const int d,
+                                              const int t0, T* __restrict__ Ln)
+{
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int LPR = NT / NMAX;
+    // opaque copy of the thread index: the lane addresses derived from it are
+    // formed again at every depth rather than hoisted out of the depth loop
+    // (where they would be spilled)
+    int t = t0;
+    asm volatile("" : "+v"(t));
+    const int lane = t & 63;
+    (void)lane;
+    const int q = t / LPR, sub = t % LPR;
+    const Node qn = node_of(q < n ? q : 0, d, n);
+    const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
+    const int qlo = qn.lo;
+    const int mq = qn.hi - qn.lo;
+    const int kq = qact ? S.u.m.nk[qlo] : 0;
+    const int jr = q - qlo;
+    const T* dk = S.u.m.dk + qlo;
+    const T* zk = S.u.m.zk + qlo;
+    const T rho = qact ? S.u.m.nrho[qlo] : T(0);
+
+    // ---- M2: secular roots --------------------------------------------------
+    {
+        constexpr int SL = LPR < 4 ? LPR : 4;
+        if (t < NMAX * SL) secular_roots<T, NMAX, NT, SL, KPL * LPR / SL>(S, n, d, t);
     }
     team_sync<NT>();
     BED_PHASE(10 + 8 * d + 1);
