@@ -85,6 +85,28 @@ template <int CTRL> __device__ __forceinline__ uint32_t dpp32(uint32_t x)
 {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)x, CTRL, 0xF, 0xF, false);
 }
+// Value of lane ^ M within each quad (M = 1, 2, 3; quad_perm [3,2,1,0] = 0x1B
+// is lane ^ 3).
+template <int M> __device__ __forceinline__ uint32_t qxor32(uint32_t x)
+{
+    static_assert(M >= 0 && M <= 3, "quad lane mask");
+    if constexpr (M == 0) return x;
+    else if constexpr (M == 1) return dpp32<0xB1>(x);
+    else if constexpr (M == 2) return dpp32<0x4E>(x);
+    else return dpp32<0x1B>(x);
+}
+template <int M> __device__ __forceinline__ float qxor(float x)
+{
+    return __uint_as_float(qxor32<M>(__float_as_uint(x)));
+}
+template <int M> __device__ __forceinline__ int qxor(int x) { return (int)qxor32<M>((uint32_t)x); }
+template <int M> __device__ __forceinline__ double qxor(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = qxor32<M>((uint32_t)b), hi = qxor32<M>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Value of lane ^ 16 (permlane16_swap exchanges odd rows of its first operand
 // with even rows of its second) and of lane ^ 32 (permlane32_swap exchanges the
 // upper half of its first operand with the lower half of its second).

@@ -115,8 +115,9 @@ struct Smem {
 };
 
 // Node of a dyadic tearing tree over [0, n): node j at depth d covers
-// [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of >= 3 elements split at
-// the floor of their dyadic midpoint.
+// [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of more than LEAF elements
+// split at the floor of their dyadic midpoint, the others are leaves.
+constexpr int LEAF = 4;
 struct Node {
     int lo, hi, s;
 };
@@ -132,34 +133,167 @@ __device__ __forceinline__ Node node_of(int e, int d, int n)
 
 __device__ __forceinline__ int node_index(int e, int d, int n) { return (((e + 1) << d) - 1) / n; }
 
-// 2x2 symmetric Schur decomposition by one Givens/Jacobi rotation (Sec. 2.2).
+// Jacobi rotation that annihilates a_pq of the symmetric 2x2 block
+// [a_pp a_pq; a_pq a_qq] (Rutishauser's form): t = tan(phi) with
+// th = (a_qq - a_pp) / (2 a_pq), t = sgn(th) / (|th| + sqrt(th^2 + 1)),
+// c = 1/sqrt(1 + t^2), s = t c.  Then a_pp' = a_pp - t a_pq, a_qq' = a_qq + t a_pq.
 template <typename T>
-__device__ __forceinline__ void leaf2(T p, T q, T r, T lam[2], T Q[4])
+__device__ __forceinline__ void jacobi_rot(const T app, const T aqq, const T apq, T& c, T& s, T& t)
 {
-    T c = T(1), s = T(0), t = T(0);
-    if (q != T(0)) {
-        if constexpr (sizeof(T) == 4) {
-            // hardware reciprocal (rcp(inf) = 0: a huge |th| gives t = 0, the
-            // rotation's limit) and square root; c^2 + s^2 = 1 to a few ulps
-            const T th = (r - p) * f_rcp_fast(T(2) * q);
-            t = (th < T(0) ? T(-1) : T(1)) * f_rcp_fast(f_abs(th) + f_sqrt(fma(th, th, T(1))));
-            c = f_rcp_fast(f_sqrt(fma(t, t, T(1))));
-        } else {
-            const T th = (r - p) / (T(2) * q);
-            t = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
-            c = T(1) / f_hypot(T(1), t);
-        }
-        s = t * c;
-    }
-    T l1 = p - t * q, l2 = r + t * q;
-    if (l1 <= l2) {
-        lam[0] = l1; lam[1] = l2;
-        Q[0] = c;  Q[1] = s;
-        Q[2] = -s; Q[3] = c;
+    T tt, cc;
+    if constexpr (sizeof(T) == 4) {
+        // hardware reciprocal (rcp(inf) = 0: a huge |th| gives t = 0, the
+        // rotation's limit) and square root; c^2 + s^2 = 1 to a few ulps
+        const T th = (aqq - app) * f_rcp_fast(T(2) * apq);
+        tt = (th < T(0) ? T(-1) : T(1)) * f_rcp_fast(f_abs(th) + f_sqrt(fma(th, th, T(1))));
+        cc = f_rcp_fast(f_sqrt(fma(tt, tt, T(1))));
     } else {
-        lam[0] = l2; lam[1] = l1;
-        Q[0] = s; Q[1] = c;
-        Q[2] = c; Q[3] = -s;
+        const T th = (aqq - app) / (T(2) * apq);
+        tt = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
+        cc = T(1) / f_hypot(T(1), tt);
+    }
+    const bool rot = apq != T(0);  // (a NaN from a zero a_pq is selected away)
+    t = rot ? tt : T(0);
+    c = rot ? cc : T(1);
+    s = rot ? tt * cc : T(0);
+}
+
+// One simultaneous round of the leaf Jacobi sweep: the pairs (i, i ^ M) of
+// every leaf.  Lane i keeps row i of A and of V = J_1 J_2 ... in XOR-relative
+// order, a[k] = A(i, i ^ k), v[k] = V(i, i ^ k).  With J the product of the
+// round's disjoint rotations, A <- J^T A J and V <- V J: each lane rotates its
+// row's column pairs (j, j ^ M) with the parameters held by lane j, then
+// combines its row with the partner row i ^ M.  The pair's own 2x2 block takes
+// the exact form (a_pq' = 0, a_pp' = a_pp - t a_pq, a_qq' = a_qq + t a_pq).
+template <int M, typename T>
+__device__ __forceinline__ void jacobi_round(T (&a)[4], T (&v)[4], const int i, const int msz)
+{
+    const int ip = i ^ M;
+    const T pd = qxor<M>(a[0]);  // A(ip, ip)
+    const T po = qxor<M>(a[M]);  // A(ip, i)
+    const bool low = i < ip;     // this row is p of the pair (p, q), p < q
+    // both lanes of the pair form the same a_pq (the rounded rows need not be
+    // exactly symmetric)
+    const T apq = T(0.5) * (a[M] + po);
+    T c, s, t;
+    jacobi_rot(low ? a[0] : pd, low ? pd : a[0], apq, c, s, t);
+    const bool rot = i < msz && ip < msz && apq != T(0);  // pairs with a padding row stay fixed
+    c = rot ? c : T(1);
+    s = rot ? s : T(0);
+    t = rot ? t : T(0);
+    const T sg = low ? T(-1) : T(1);  // A'(p, :) = c A(p, :) - s A(q, :), A'(q, :) = c A(q, :) + s A(p, :)
+    const T ss = sg * s;
+    // column parameters (c_j, sigma_j s_j) of column j = i ^ k
+    T cj[4], sj[4];
+    cj[0] = c;
+    sj[0] = ss;
+    cj[M] = c;
+    sj[M] = -ss;
+    if constexpr (M != 1) {
+        cj[1] = qxor<1>(c);
+        sj[1] = qxor<1>(ss);
+    }
+    if constexpr (M != 2) {
+        cj[2] = qxor<2>(c);
+        sj[2] = qxor<2>(ss);
+    }
+    if constexpr (M != 3) {
+        cj[3] = qxor<3>(c);
+        sj[3] = qxor<3>(ss);
+    }
+    T b[4], w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        b[k] = fma(sj[k], a[k ^ M], cj[k] * a[k]);
+        w[k] = fma(sj[k], v[k ^ M], cj[k] * v[k]);
+    }
+    // partner row after its column rotation: B(ip, i ^ k) sits in its slot k ^ M
+    T pb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pb[k] = qxor<M>(b[k ^ M]);
+    const T dnew = fma(sg * t, apq, a[0]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = fma(ss, pb[k], c * b[k]);
+        v[k] = w[k];
+    }
+    a[0] = rot ? dnew : a[0];
+    a[M] = rot ? T(0) : a[M];
+}
+
+// Leaves of at most LEAF elements are solved by cyclic Jacobi (the divide step
+// may stop at small blocks and hand them to another eigensolver, Sec. 2.2).
+// Wave 0: lane (g, i) = (lane / 4, lane % 4) holds row i of the leaf of group
+// g, group g standing for node g of depth D (the first such node of a leaf
+// owns it).  Sweeps of the pairs (i, i ^ m), m = 1, 2, 3, run until every
+// off-diagonal entry is at most 8u ||T_leaf||_F (the wave's largest); the
+// eigenvalues are then ranked ascending and the leaf's block of Q written.
+template <typename T, int NMAX, int NT>
+__device__ __forceinline__ void jacobi_leaves(Smem<T, NMAX, NT>& S, const int n, const int D,
+                                              const int lane, T* __restrict__ Qc,
+                                              T* __restrict__ Lc)
+{
+    static_assert(LEAF == 4 && NMAX <= 64, "at most 16 leaf groups of four lanes");
+    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int CAP = 16;  // sweeps (three suffice in binary32 and binary64 alike)
+    const int g = lane >> 2, i = lane & 3;
+    const int e0 = (g * n) >> D;  // first element of node g at depth D
+    int lo = 0, hi = 0;
+    bool found = false;
+    for (int d = 0; d <= D; ++d) {
+        const Node nd = node_of(e0 < n ? e0 : 0, d, n);
+        const bool hit = !found && nd.hi - nd.lo <= LEAF;
+        lo = hit ? nd.lo : lo;
+        hi = hit ? nd.hi : hi;
+        found = found || hit;
+    }
+    const bool own = g < (1 << D) && found && lo == e0;
+    const int msz = own ? hi - lo : 0;
+    const bool row = i < msz;
+    T a[4], v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int j = i ^ k;
+        const bool ok = row && j < msz;
+        const bool adj = j == i + 1 || j == i - 1;
+        const int bi = lo + (i < j ? i : j);
+        T x = T(0);
+        if (k == 0) x = S.a[ok ? lo + i : 0];
+        else if (adj) x = S.b[ok ? bi : 0];
+        a[k] = ok ? x : T(0);
+        v[k] = (k == 0) ? T(1) : T(0);
+    }
+    T f2 = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f2 = fma(a[k], a[k], f2);
+    f2 = group_sum<4>(f2, lane);
+    const T thr = T(8) * fp<T>::u * f_sqrt(f2);
+    for (int sw = 0; sw < CAP; ++sw) {
+        const T off = f_max(f_abs(a[1]), f_max(f_abs(a[2]), f_abs(a[3])));
+        if (!__ballot(off > thr)) break;
+        jacobi_round<1>(a, v, i, msz);
+        jacobi_round<2>(a, v, i, msz);
+        jacobi_round<3>(a, v, i, msz);
+    }
+    // ascending rank of this row's eigenvalue among the leaf's (ties by index)
+    int rk = 0;
+    {
+        const T o1 = qxor<1>(a[0]), o2 = qxor<2>(a[0]), o3 = qxor<3>(a[0]);
+        rk += ((i ^ 1) < msz && (o1 < a[0] || (o1 == a[0] && (i ^ 1) < i))) ? 1 : 0;
+        rk += ((i ^ 2) < msz && (o2 < a[0] || (o2 == a[0] && (i ^ 2) < i))) ? 1 : 0;
+        rk += ((i ^ 3) < msz && (o3 < a[0] || (o3 == a[0] && (i ^ 3) < i))) ? 1 : 0;
+    }
+    int rj[4];
+    rj[0] = rk;
+    rj[1] = qxor<1>(rk);
+    rj[2] = qxor<2>(rk);
+    rj[3] = qxor<3>(rk);
+    if (row) {
+        Lc[lo + rk] = a[0];
+        // V(i, j) is entry i of the eigenvector of eigenvalue j
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if ((i ^ k) < msz) Qc[(lo + i) * LD + lo + rj[k]] = v[k];
     }
 }
 
@@ -235,7 +369,7 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
     const T FAR = sizeof(T) == 4 ? T(1e30f) : T(1e300);
     const int q = t / LPR, sub = t % LPR;
     const Node qn = node_of(q < n ? q : 0, d, n);
-    const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
+    const bool qact = (q < n) && (qn.hi - qn.lo > LEAF);
     const int qlo = qn.lo;
     const int kq = qact ? S.u.m.nk[qlo] : 0;
     const int jr = q - qlo;
@@ -406,7 +540,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     (void)lane;
     const int q = t / LPR, sub = t % LPR;
     const Node qn = node_of(q < n ? q : 0, d, n);
-    const bool qact = (q < n) && (qn.hi - qn.lo >= 3);
+    const bool qact = (q < n) && (qn.hi - qn.lo > LEAF);
     const int qlo = qn.lo;
     const int mq = qn.hi - qn.lo;
     const int kq = qact ? S.u.m.nk[qlo] : 0;
@@ -962,8 +1096,8 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     BED_PHASE(2);
 
     // ------------------------------------------------------------ tear + leaves
-    int D = 0;
-    while (((n + (1 << D) - 1) >> D) > 2) ++D;
+    int D = 0;  // depth of the smallest leaves
+    while (((n + (1 << D) - 1) >> D) > LEAF) ++D;
     T* Qc = S.Q0;
     T* Qn = S.Q1;
     T* Lc = S.lam0;
@@ -971,37 +1105,18 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     if (wave == 0) {
         const int e = lane;
         T ae = (e < n) ? S.a[e] : T(0);
-        // Eq. (3): every split s of a node with >= 3 elements subtracts |b_{s-1}|
-        // from a_{s-1} and a_s (ancestors first).
-        // (branch-free: every depth's coupling is read from a clamped address
-        // and applied by a select; the leaf is the first node of size <= 2)
-        int llo = e, lhi = e + 1;
-        bool found = false;
-        for (int d = 0; d <= D; ++d) {
+        // Eq. (3): every split s of a node with more than LEAF elements
+        // subtracts |b_{s-1}| from a_{s-1} and a_s (branch-free: every depth's
+        // coupling is read from a clamped address and applied by a select)
+        for (int d = 0; d < D; ++d) {
             const Node nd = node_of(e < n ? e : 0, d, n);
-            const bool split = d < D && nd.hi - nd.lo >= 3 && (e == nd.s - 1 || e == nd.s);
+            const bool split = nd.hi - nd.lo > LEAF && (e == nd.s - 1 || e == nd.s);
             const T bs = S.b[nd.s >= 1 ? nd.s - 1 : 0];
             ae -= (e < n && split) ? f_abs(bs) : T(0);
-            const bool leaf = !found && nd.hi - nd.lo <= 2;
-            llo = leaf ? nd.lo : llo;
-            lhi = leaf ? nd.hi : lhi;
-            found = found || leaf;
         }
         if (e < n) S.a[e] = ae;  // torn diagonal
         wave_sync();
-        if (e < n) {
-            if (lhi - llo == 1) {
-                Lc[e] = ae;
-                Qc[e * LD + e] = T(1);
-            } else {
-                T l2[2], q2[4];
-                leaf2(S.a[llo], S.b[llo], S.a[llo + 1], l2, q2);
-                const bool second = e != llo;
-                Lc[e] = second ? l2[1] : l2[0];
-                Qc[e * LD + llo] = second ? q2[2] : q2[0];
-                Qc[e * LD + llo + 1] = second ? q2[3] : q2[1];
-            }
-        }
+        jacobi_leaves<T, NMAX, NT>(S, n, D, lane, Qc, Lc);
     }
     team_sync<NT>();
     BED_PHASE(3);
@@ -1013,7 +1128,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         if (wave == NW - 1) {
             const int e = lane;
             const Node nd = node_of(e < n ? e : 0, d, n);
-            const bool act = (e < n) && (nd.hi - nd.lo >= 3);
+            const bool act = (e < n) && (nd.hi - nd.lo > LEAF);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
             {
                 // Rows of a leaf that is not merged at this depth pass through
@@ -1045,7 +1160,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const int e = lane;
             const Node nd = node_of(e < n ? e : 0, d, n);
             BED_MARK(d, 8);
-            const bool act = (e < n) && (nd.hi - nd.lo >= 3);
+            const bool act = (e < n) && (nd.hi - nd.lo > LEAF);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
             const T bet = act ? S.b[s - 1] : T(0);
             const T rho = f_abs(bet);
@@ -1243,7 +1358,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             BED_MARK(d, 2);
             // eigenvalues of nodes not merged at this depth
             for (int e = t; e < n; e += NT) {
-                if (S.u.m.nhi[e] - S.u.m.nlo[e] < 3) Ln[e] = Lc[e];
+                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= LEAF) Ln[e] = Lc[e];
             }
             BED_MARK(d, 3);
         }
