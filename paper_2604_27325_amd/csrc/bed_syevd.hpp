@@ -463,22 +463,22 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
             L = up ? T(0) : (topr ? h : h - gap);
             U = up ? h : (topr ? top : T(0));
             // Eq. (16): one multi-section probe toward the origin pole while the
-            // bracket is wide, then Halley from the bracket midpoint
+            // bracket is wide; Halley steps start from the probe's point
             const bool probe = (U - L) > T(1e-2) * w0;
             const T hp = shift ? U - T(0.25) * (U - L) : L + T(0.25) * (U - L);
             const bool stop = live && f == T(0);
             why = stop ? 1 : 0;
             done = done || stop;
             h = stop ? h : (probe ? hp : T(0.5) * (L + U));
-            nhal = probe ? -1 : 0;  // -1: the next evaluation is the probe
+            nhal = probe ? -1 : 0;  // evaluations after the probe count toward the cap
         }
         // Progressive removal (Eq. (22)): a converged root's lanes idle; the
         // wave leaves the loop once all of its roots have stopped.  The body
         // is select-based: every live root updates its bracket by the sign of
-        // f (Eq. (14)); after the probe the next point is the midpoint, after a
-        // Halley evaluation it is Halley's point if inside the bracket, else
-        // the root of the one-pole model f ~ c - ao/tau through (h, f) (exact
-        // next to a light origin pole), else the midpoint.  A root stops at
+        // f (Eq. (14)); the next point is Halley's from the evaluated point
+        // (the probe's included) if inside the bracket, else the root of the
+        // one-pole model f ~ c - ao/tau through (h, f) (exact next to a light
+        // origin pole), else the midpoint.  A root stops at
         // f = 0 or |f| <= eb, at a bracket with no interior float, when the
         // step does not move h, or at the cap.
         while (__ballot(!done)) {
@@ -486,19 +486,18 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
             nev += done ? 0 : 1;
             T f, f1, f2, eb;
             secular(h, f, f1, f2, eb);
-            const bool hal = nhal >= 0;
-            const bool conv = f == T(0) || (hal && f_abs(f) <= eb);
+            const bool conv = f == T(0) || f_abs(f) <= eb;
             const bool up = f > T(0);
             const T U2 = up ? h : U;
             const T L2 = up ? L : h;
-            const bool tight = hal && (U2 - L2) <= T(2) * u * (f_abs(L2) + f_abs(U2));
+            const bool tight = (U2 - L2) <= T(2) * u * (f_abs(L2) + f_abs(U2));
             const T den = T(2) * f1 * f1 - f * f2;
             const T hh = h - T(2) * f * f1 * f_rcp_fast(den);
             const T hm = ao * h * f_rcp_fast(fma(f, h, ao));
             const bool okh = den > T(0) && hh > L2 && hh < U2;
             const bool okm = hm > L2 && hm < U2;
             const T mid = T(0.5) * (L2 + U2);
-            const T hn = hal ? (okh ? hh : (okm ? hm : mid)) : mid;
+            const T hn = okh ? hh : (okm ? hm : mid);
             const bool step = !(conv || tight) && hn != h;
             const int nh = nhal + 1;
             const bool cap = step && nh >= SEC_CAP;
