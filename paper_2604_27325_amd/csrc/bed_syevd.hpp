@@ -1453,22 +1453,41 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         }
         team_sync<NT>();
         BED_PHASE(4);
-        // parts in increasing row order: a later part wins only when strictly
-        // larger in magnitude
-        for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+        // Sign of column j: parts in increasing row order, a later part wins
+        // only when strictly larger in magnitude.  16-byte stores when the
+        // rows allow them, as for the load.
+        auto colsign = [&](const int j) {
             T bv = S.u.b.gram[j];
 #pragma unroll
             for (int pp = 1; pp < WPC; ++pp) {
                 const T o = S.u.b.gram[pp * NMAX + j];
                 bv = (f_abs(o) > f_abs(bv)) ? o : bv;
             }
-            const T x = Qn[i * LD + j];
-            Q_out[e] = (bv < T(0)) ? -x : x;
-            j += NT % n;
-            i += NT / n;
-            if (j >= n) {
-                j -= n;
-                ++i;
+            return bv;
+        };
+        if (n % VW == 0 && (reinterpret_cast<uintptr_t>(Q_out) & 15) == 0) {
+            vec_t* Qv = reinterpret_cast<vec_t*>(Q_out);
+            const int nv = n * n / VW;
+            for (int e = t; e < nv; e += NT) {
+                const int i = (e * VW) / n, j = (e * VW) % n;
+                vec_t x;
+#pragma unroll
+                for (int q4 = 0; q4 < VW; ++q4) {
+                    const T y = Qn[i * LD + j + q4];
+                    x[q4] = (colsign(j + q4) < T(0)) ? -y : y;
+                }
+                Qv[e] = x;
+            }
+        } else {
+            for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
+                const T x = Qn[i * LD + j];
+                Q_out[e] = (colsign(j) < T(0)) ? -x : x;
+                j += NT % n;
+                i += NT / n;
+                if (j >= n) {
+                    j -= n;
+                    ++i;
+                }
             }
         }
         for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
