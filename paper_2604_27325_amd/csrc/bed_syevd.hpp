@@ -462,15 +462,25 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
             }
             L = up ? T(0) : (topr ? h : h - gap);
             U = up ? h : (topr ? top : T(0));
-            // Eq. (16): one multi-section probe toward the origin pole while the
-            // bracket is wide; Halley steps start from the probe's point
+            // The next point is Halley's from the midpoint (in the shifted
+            // variable when the origin moved) when that step is short (within
+            // a quarter of the bracket: the root lies near the midpoint), else
+            // (Eq. (16)) one multi-section probe toward the origin pole while
+            // the bracket is wide, else the one-pole model's point, else the
+            // midpoint.
+            const T hs = shift ? h - gap : h;  // the evaluated point, from the new origin
+            const T den = T(2) * f1 * f1 - f * f2;
+            const T hh = hs - T(2) * f * f1 * f_rcp_fast(den);
+            const T hm = ao * hs * f_rcp_fast(fma(f, hs, ao));
+            const bool okh = den > T(0) && hh > L && hh < U && f_abs(hh - hs) <= T(0.25) * (U - L);
+            const bool okm = hm > L && hm < U;
             const bool probe = (U - L) > T(1e-2) * w0;
             const T hp = shift ? U - T(0.25) * (U - L) : L + T(0.25) * (U - L);
             const bool stop = live && f == T(0);
             why = stop ? 1 : 0;
             done = done || stop;
-            h = stop ? h : (probe ? hp : T(0.5) * (L + U));
-            nhal = probe ? -1 : 0;  // evaluations after the probe count toward the cap
+            h = stop ? h : (okh ? hh : (probe ? hp : (okm ? hm : T(0.5) * (L + U))));
+            nhal = 0;
         }
         // Progressive removal (Eq. (22)): a converged root's lanes idle; the
         // wave leaves the loop once all of its roots have stopped.  The body
