@@ -77,6 +77,26 @@ __device__ __forceinline__ void team_sync()
         wave_sync();
 }
 
+// Biased binary exponent field of x (0 for zero and subnormals) and the exact
+// power of two 2^s (|s| at most SMAX, so that it stays a normal number).
+__device__ __forceinline__ int exp_field(float x) { return (int)((__float_as_uint(x) >> 23) & 0xFFu); }
+__device__ __forceinline__ int exp_field(double x)
+{
+    return (int)(((uint64_t)__double_as_longlong(x) >> 52) & 0x7FFu);
+}
+template <typename T> struct fexp;
+template <> struct fexp<float> {
+    static constexpr int BIAS = 127, SMAX = 100;
+    static __device__ __forceinline__ float pow2(int s) { return __uint_as_float((uint32_t)(BIAS + s) << 23); }
+};
+template <> struct fexp<double> {
+    static constexpr int BIAS = 1023, SMAX = 1000;
+    static __device__ __forceinline__ double pow2(int s)
+    {
+        return __longlong_as_double((long long)((uint64_t)(BIAS + s) << 52));
+    }
+};
+
 // ---- cross-lane moves --------------------------------------------------------
 // DPP controls: quad_perm [1,0,3,2] = 0xB1 (lane ^ 1), [2,3,0,1] = 0x4E
 // (lane ^ 2), row_half_mirror = 0x141 (lane ^ 7 within 8), row_mirror = 0x140

@@ -110,6 +110,7 @@ struct Smem {
         } b;
     } u;
     int badw[NW];
+    int expw[NW];  // per wave: largest exponent field of the lower triangle
     int capped;
     int anyrot;
 };
@@ -921,7 +922,7 @@ __device__ __forceinline__ bool hh_barrier_at(const int k)
 
 template <typename T, int NMAX, int NT, int HW>
 __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, const int lane,
-                                           const int wave, const bool want_q,
+                                           const int wave, const bool want_q, const T sc,
                                            T (&qh)[QhShape<T, NMAX, NT>::VPL])
 {
     constexpr int LD = Smem<T, NMAX, NT>::LD;
@@ -967,9 +968,9 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int c = g + G * j;
-        ar[j] = (r < n && c < n) ? (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
+        ar[j] = (r < n && c < n) ? sc * (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
     }
-    T xr = (r < n) ? S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
+    T xr = (r < n) ? sc * S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
     T sig = wave_total((g0 && r > 1) ? xr * xr : T(0));
     // reflector of step 0 (harmless when n <= 2, as above)
     const HhRefl<T> h = hh_reflector(bcast(xr, 1), sig);
@@ -1019,10 +1020,12 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     // ------------------------------------------------------------ load
     // 16-byte loads when the rows allow it (n a multiple of the vector width
     // and A 16-byte aligned), else one element per thread and step.  A
-    // non-finite entry of the lower triangle is flagged per wave by a ballot.
+    // non-finite entry of the lower triangle is flagged per wave by a ballot,
+    // and the largest magnitude's exponent is kept for the scaling below.
     {
         constexpr int VW = 16 / sizeof(T);
         bool bad = false;
+        T amax = T(0);
         if (n % VW == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0) {
             typedef T vec_t __attribute__((ext_vector_type(VW)));
             const vec_t* Av = reinterpret_cast<const vec_t*>(Ain);
@@ -1033,6 +1036,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
 #pragma unroll
                 for (int q = 0; q < VW; ++q) {
                     if (j + q <= i && !f_finite(v[q])) bad = true;
+                    amax = (j + q <= i) ? f_max(amax, f_abs(v[q])) : amax;
                     S.M[i * LD + j + q] = v[q];
                 }
             }
@@ -1040,6 +1044,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
                 T v = Ain[e];
                 if (j <= i && !f_finite(v)) bad = true;  // lower triangle only
+                amax = (j <= i) ? f_max(amax, f_abs(v)) : amax;
                 S.M[i * LD + j] = v;
                 j += NT % n;
                 i += NT / n;
@@ -1050,13 +1055,29 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             }
         }
         const bool wbad = __ballot(bad) != 0;
-        if (lane == 0) S.badw[wave] = wbad ? 1 : 0;
+        const int wexp = group_max<64>(exp_field(amax), lane);
+        if (lane == 0) {
+            S.badw[wave] = wbad ? 1 : 0;
+            S.expw[wave] = wexp;
+        }
         if (t == 0) S.capped = 0;
     }
     team_sync<NT>();
-    int anybad = 0;
+    int anybad = 0, emax = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) anybad |= S.badw[w];
+    for (int w = 0; w < NW; ++w) {
+        anybad |= S.badw[w];
+        emax = max(emax, S.expw[w]);
+    }
+    // The solver runs on 2^s A with max |a_ij| in [1/2, 1) (s clamped, 0 for a
+    // zero matrix): the scaling is exact, and keeps the secular offsets of
+    // roots next to their poles out of the subnormal range, where the
+    // hardware reciprocal flushes.  Eigenvalues are scaled back on output;
+    // eigenvectors do not change.
+    emax = __builtin_amdgcn_readfirstlane(emax);  // uniform: keep it (and sc) scalar
+    int sh = (emax == 0) ? 0 : fexp<T>::BIAS - 1 - emax;
+    sh = min(max(sh, -fexp<T>::SMAX), fexp<T>::SMAX);
+    const T sc = fexp<T>::pow2(sh), isc = fexp<T>::pow2(-sh);
     if (anybad) {
         if (Q_out)
             for (int e = t; e < n * n; e += NT) Q_out[e] = f_nan<T>();
@@ -1071,7 +1092,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
     const bool qh_wave = AW > 0 && wave >= HW && wave < HW + AW && Q_out != nullptr;
     T qh[QhShape<T, NMAX, NT>::VPL];
-    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr, qh);
+    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr, sc, qh);
     team_sync<NT>();
     if constexpr (AW > 0) {
         // reflectors written after the last barrier of the reduction
@@ -1378,7 +1399,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     }
 
     if (!Q_out) {  // eigenvalues only
-        for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+        for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
         if (t == 0 && info_out) *info_out = S.capped;
         return;
     }
@@ -1500,7 +1521,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 }
             }
         }
-        for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+        for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
         if (t == 0 && info_out) *info_out = S.capped;
         BED_PHASE(5);
         return;
@@ -1681,7 +1702,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             ++i;
         }
     }
-    for (int e = t; e < n; e += NT) lam_out[e] = Lc[e];
+    for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
     if (t == 0 && info_out) *info_out = S.capped;
     BED_PHASE(5);
     }

@@ -126,3 +126,26 @@ def test_batch_zero_is_noop():
     A = torch.empty(0, device=DEV)
     lam, Q, info = bed.syevd_packed([], A)
     assert lam.numel() == 0 and Q.numel() == 0
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_scaled_and_block_structured_matrices(dt):
+    """Scale invariance (every threshold is relative) at sizes that are a single
+    leaf, one merge, ragged and full; block-diagonal input (zero couplings in
+    the tridiagonal form, exactly repeated eigenvalues from repeated blocks);
+    Wilkinson's W21+ (pairs agreeing to many digits)."""
+    rng = np.random.default_rng(77)
+    s_hi, s_lo = (1e12, 1e-12) if dt == np.float32 else (1e100, 1e-100)
+    mats = []
+    for n in (4, 5, 8, 37, 64):
+        G = workloads.gaussian_sym(rng, 1, n)[0]
+        mats += [G * s_hi, G * s_lo]
+    blk = workloads.gaussian_sym(rng, 1, 4)[0]
+    B = np.zeros((24, 24))
+    for b in range(6):
+        B[4 * b:4 * b + 4, 4 * b:4 * b + 4] = blk if b % 2 == 0 else workloads.gaussian_sym(rng, 1, 4)[0]
+    mats.append(B)
+    W = np.diag(np.abs(np.arange(-10.0, 11.0))) + np.diag(np.ones(20), 1) + np.diag(np.ones(20), -1)
+    mats.append(W)
+    for i, M in enumerate(mats):
+        check(M[None].astype(dt), f"scaled/block {i} n={M.shape[0]} {dt.__name__}")
