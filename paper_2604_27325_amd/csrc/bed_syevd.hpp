@@ -115,6 +115,23 @@ struct Smem {
     int anyrot;
 };
 
+// The solver runs on 2^s A with max |a_ij| in [1/2, 1) (s clamped, 0 for a
+// zero matrix): the scaling is exact, and keeps the secular offsets of roots
+// next to their poles out of the subnormal range, where the hardware
+// reciprocal flushes.  Eigenvalues are scaled back on output; eigenvectors do
+// not change.  s comes from the per-wave exponents the load leaves in LDS
+// (formed where it is needed, so that it holds no registers in between).
+template <typename T, int NMAX, int NT>
+__device__ __forceinline__ int input_shift(const Smem<T, NMAX, NT>& S)
+{
+    int emax = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) emax = max(emax, S.expw[w]);
+    emax = __builtin_amdgcn_readfirstlane(emax);
+    const int sh = (emax == 0) ? 0 : fexp<T>::BIAS - 1 - emax;
+    return min(max(sh, -fexp<T>::SMAX), fexp<T>::SMAX);
+}
+
 // Node of a dyadic tearing tree over [0, n): node j at depth d covers
 // [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of more than LEAF elements
 // split at the floor of their dyadic midpoint, the others are leaves.
@@ -1063,21 +1080,9 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         if (t == 0) S.capped = 0;
     }
     team_sync<NT>();
-    int anybad = 0, emax = 0;
+    int anybad = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        anybad |= S.badw[w];
-        emax = max(emax, S.expw[w]);
-    }
-    // The solver runs on 2^s A with max |a_ij| in [1/2, 1) (s clamped, 0 for a
-    // zero matrix): the scaling is exact, and keeps the secular offsets of
-    // roots next to their poles out of the subnormal range, where the
-    // hardware reciprocal flushes.  Eigenvalues are scaled back on output;
-    // eigenvectors do not change.
-    emax = __builtin_amdgcn_readfirstlane(emax);  // uniform: keep it (and sc) scalar
-    int sh = (emax == 0) ? 0 : fexp<T>::BIAS - 1 - emax;
-    sh = min(max(sh, -fexp<T>::SMAX), fexp<T>::SMAX);
-    const T sc = fexp<T>::pow2(sh), isc = fexp<T>::pow2(-sh);
+    for (int w = 0; w < NW; ++w) anybad |= S.badw[w];
     if (anybad) {
         if (Q_out)
             for (int e = t; e < n * n; e += NT) Q_out[e] = f_nan<T>();
@@ -1092,7 +1097,8 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
     const bool qh_wave = AW > 0 && wave >= HW && wave < HW + AW && Q_out != nullptr;
     T qh[QhShape<T, NMAX, NT>::VPL];
-    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr, sc, qh);
+    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr,
+                                          fexp<T>::pow2(input_shift(S)), qh);
     team_sync<NT>();
     if constexpr (AW > 0) {
         // reflectors written after the last barrier of the reduction
@@ -1399,7 +1405,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     }
 
     if (!Q_out) {  // eigenvalues only
-        for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
+        for (int e = t; e < n; e += NT) lam_out[e] = fexp<T>::pow2(-input_shift(S)) * Lc[e];
         if (t == 0 && info_out) *info_out = S.capped;
         return;
     }
@@ -1521,7 +1527,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 }
             }
         }
-        for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
+        for (int e = t; e < n; e += NT) lam_out[e] = fexp<T>::pow2(-input_shift(S)) * Lc[e];
         if (t == 0 && info_out) *info_out = S.capped;
         BED_PHASE(5);
         return;
@@ -1702,7 +1708,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             ++i;
         }
     }
-    for (int e = t; e < n; e += NT) lam_out[e] = isc * Lc[e];
+    for (int e = t; e < n; e += NT) lam_out[e] = fexp<T>::pow2(-input_shift(S)) * Lc[e];
     if (t == 0 && info_out) *info_out = S.capped;
     BED_PHASE(5);
     }
