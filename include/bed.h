@@ -38,7 +38,10 @@
  *                k>0 k secular roots stopped at the iteration cap (results
  *                    returned, accuracy not guaranteed).
  *   Threads    calls on distinct plans/streams are thread-safe; a server is
- *              internally synchronized.
+ *              internally synchronized.  One plan runs on one stream at a
+ *              time: a persistent plan's work counter belongs to the plan,
+ *              so runs of one plan must not overlap (create a plan per
+ *              stream; the convenience entry points do so internally).
  */
 #ifndef BED_H
 #define BED_H
@@ -83,8 +86,10 @@ typedef struct bed_tune {
 typedef struct bed_plan bed_plan;
 
 /* One-shot solve: lambda, Q (and info) for a packed batch.  batch == 0 is a
- * no-op.  Uses an internal plan cache keyed by (dtype, n[]); the first call
- * for a new mixed-size n[] allocates its descriptor (refused under capture). */
+ * no-op.  A uniform batch is one launch with no descriptor.  Mixed sizes (or
+ * a stored persistent schedule) use a plan from an internal cache keyed by
+ * (dtype, n[], stream); the first call for a new key allocates its descriptor
+ * (refused under capture, BED_ERR_CAPTURE). */
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);
 
@@ -114,6 +119,20 @@ void bed_plan_destroy(bed_plan *plan);
  * buffers of the packed sizes.  The chosen schedule is written to *out. */
 bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                         void *Q, void *stream, bed_tune *out);
+
+/* Stores `tune` as the schedule of this (dtype, size mix) in the process
+ * cache, where bed_syevd, bed_syevals and bed_plan_create (tune == NULL) find
+ * it, exactly as bed_autotune stores its winner.  Launches nothing.
+ * BED_ERR_INVALID_ARG for unsupported thread counts. */
+bed_status bed_tune_set(bed_dtype dt, int64_t batch, const int32_t *n, const bed_tune *tune);
+
+/* Plans held by the convenience entry points' cache (bed_syevd and
+ * bed_syevals with mixed sizes or a persistent schedule).  The cache keeps one
+ * plan per (dtype, size mix, stream), at most 32 (least recently used evicted
+ * once its last launch has completed), except that plans used under stream
+ * capture are kept for the life of the process (a graph holds their device
+ * pointers). */
+int32_t bed_cache_entries(void);
 
 /* Backward of A = Q diag(lambda) Q^T (for differentiable use, Sec. 1):
  *   dA = Q ( diag(dlambda) + sym(F o (Q^T dQ)) ) Q^T,  sym(X) = (X + X^T)/2,
@@ -146,10 +165,14 @@ typedef struct bed_server bed_server;
 
 bed_status bed_server_create(bed_server **s, const bed_server_opts *o);
 /* Admits one request of `count` matrices of size n (packed as above).  Returns
- * BED_ERR_BUSY when admission is refused by the slot or memory limit (nothing
- * is queued; retry later).  *ticket identifies the request. */
+ * BED_ERR_BUSY when admission is refused by the in-flight or memory limit
+ * (nothing is queued; retry later).  `stream` is the caller's stream that
+ * produces A: the server records an event on it at admission and the step
+ * that reads A waits for that event, so A may still be being written by work
+ * enqueued on `stream` before this call.  *ticket identifies the request. */
 bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t count, int32_t n, const void *A,
-                             void *lambda, void *Q, int32_t *info, uint64_t *ticket);
+                             void *lambda, void *Q, int32_t *info, void *stream,
+                             uint64_t *ticket);
 /* *done = 1 once the request's results are complete in device memory;
  * *latency_us (may be NULL) = submit-to-completion-observed time. */
 bed_status bed_server_poll(bed_server *s, uint64_t ticket, int32_t *done, double *latency_us);

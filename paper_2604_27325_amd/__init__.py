@@ -13,7 +13,8 @@ import ctypes
 import os
 
 __all__ = ["syevd", "syevals", "syevd_packed", "syevd_backward", "eigh", "SyevdFn", "Plan",
-           "Server", "autotune", "BedError", "library_path", "load_library", "Tune"]
+           "Server", "autotune", "tune_set", "cache_entries", "BedError", "library_path",
+           "load_library", "Tune"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_lib", "libbed.so")
@@ -70,11 +71,13 @@ def load_library():
     lib.bed_plan_destroy.argtypes = [vp]
     lib.bed_plan_destroy.restype = None
     lib.bed_autotune.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, ctypes.POINTER(Tune)]
+    lib.bed_tune_set.argtypes = [ctypes.c_int, i64, i32p, ctypes.POINTER(Tune)]
+    lib.bed_cache_entries.restype = ctypes.c_int32
     lib.bed_syevd_backward.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, vp,
                                        ctypes.c_double, vp]
     lib.bed_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(ServerOpts)]
     lib.bed_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.c_int32, vp, vp,
-                                      vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+                                      vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.bed_server_poll.argtypes = [vp, ctypes.c_uint64, i32p, ctypes.POINTER(ctypes.c_double)]
     lib.bed_server_drain.argtypes = [vp]
     lib.bed_server_destroy.argtypes = [vp]
@@ -289,6 +292,20 @@ def autotune(dtype, n_list, A, lam, Q, stream=None):
     return t.as_dict()
 
 
+def tune_set(dtype, n_list, tune):
+    """Stores a schedule (dict or Tune) for this size mix in the process cache."""
+    lib = load_library()
+    n_arr, n_ptr = _n_array(n_list)
+    t = Tune(**{k: int(tune.get(k, 0)) for k, _ in Tune._fields_}) if isinstance(tune, dict) \
+        else tune
+    _check(lib.bed_tune_set(_dtype_code(dtype), len(n_arr), n_ptr, ctypes.byref(t)))
+
+
+def cache_entries():
+    """Plans currently held by the convenience entry points' cache."""
+    return int(load_library().bed_cache_entries())
+
+
 class Server:
     """Continuous-batching eigendecomposition server (see bed_server_* in bed.h)."""
 
@@ -299,15 +316,17 @@ class Server:
         _check(lib.bed_server_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h
 
-    def submit(self, A, lam, Q, info=None):
+    def submit(self, A, lam, Q, info=None, stream=None):
         """A: (count, n, n) GPU tensor; returns a ticket or None when admission
-        is refused (BED_ERR_BUSY)."""
+        is refused (BED_ERR_BUSY).  The request's step waits for the work
+        enqueued so far on `stream` (torch's current stream by default), the
+        producer of A."""
         count, n = A.shape[0], A.shape[1]
         tk = ctypes.c_uint64()
         st = _lib.bed_server_submit(self._h, _dtype_code(A.dtype), count, n, _dev(A, "A"),
                                     _dev(lam, "lambda"), _dev(Q, "Q"),
                                     _dev(info, "info") if info is not None else None,
-                                    ctypes.byref(tk))
+                                    _stream_ptr(stream), ctypes.byref(tk))
         if st == BED_ERR_BUSY:
             return None
         _check(st)

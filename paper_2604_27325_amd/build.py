@@ -3,7 +3,8 @@
     python -m paper_2604_27325_amd.build        # or: from ... import build; build.build()
 
 Objects go to paper_2604_27325_amd/_build/, the library to
-paper_2604_27325_amd/_lib/libbed.so.
+paper_2604_27325_amd/_lib/libbed.so, and the instrumented measurement copy of
+the solver (include/bed_probe.h) to paper_2604_27325_amd/_lib/libbed_probe.so.
 """
 import concurrent.futures
 import os
@@ -15,11 +16,13 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libbed.so")
+PROBE_LIB = os.path.join(LIB_DIR, "libbed_probe.so")
 ARCH = os.environ.get("BED_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["bed_kernels.hip", "bed_backward.hip", "bed_api.cpp", "bed_backward_api.cpp",
            "bed_tune.cpp", "bed_server.cpp"]
+PROBE_SOURCES = ["bed_probe.hip"]
 
 # Every HIP translation unit is compiled with packed-FP32 instruction
 # selection disabled (plain float code only).
@@ -38,19 +41,24 @@ def _compile(src):
     return obj, msgs
 
 
+def _link(objs, lib):
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp] + objs + ["-lpthread"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, lib)
+
+
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
     os.makedirs(LIB_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
-        results = list(ex.map(_compile, SOURCES))
-    for obj, msgs in results:
+    srcs = SOURCES + PROBE_SOURCES
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(srcs), 7)) as ex:
+        results = dict(zip(srcs, ex.map(_compile, srcs)))
+    for obj, msgs in results.values():
         if verbose and msgs.strip():
             print(msgs, file=sys.stderr)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp] + [o for o, _ in results] + \
-        ["-lpthread"]
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    _link([results[s][0] for s in SOURCES], LIB)
+    _link([results[s][0] for s in PROBE_SOURCES], PROBE_LIB)
     return LIB
 
 

@@ -15,6 +15,7 @@
 #include "../../include/bed.h"
 #include "bed_internal.hpp"
 #include "bed_host.hpp"
+#include "bed_lru.hpp"
 
 using namespace bed;
 
@@ -263,18 +264,39 @@ extern "C" void bed_plan_destroy(bed_plan *plan)
 }
 
 // ------------------------------------------------------------------ plan cache
+// bed_syevd / bed_syevals keep one plan per (dtype, n[], stream): a persistent
+// plan's work counter is then never shared by launches on two streams.  The
+// cache holds at most PLAN_CACHE_MAX plans; an evicted plan is freed after the
+// event recorded behind its last launch has completed.  A plan used while its
+// stream is being captured is pinned: the graph holds its device pointers.
 namespace {
 struct CacheKey {
     bed_dtype dt;
+    void *stream;
     std::vector<int32_t> n;
     bool operator<(const CacheKey &o) const
     {
         if (dt != o.dt) return dt < o.dt;
+        if (stream != o.stream) return stream < o.stream;
         return n < o.n;
     }
 };
+struct CachedPlan {
+    bed_plan *plan = nullptr;
+    hipEvent_t last = nullptr;  // recorded after the latest (uncaptured) launch
+};
+constexpr size_t PLAN_CACHE_MAX = 32;
 std::mutex g_cache_mu;
-std::map<CacheKey, bed_plan *> g_cache;
+Lru<CacheKey, CachedPlan> g_cache(PLAN_CACHE_MAX);
+
+void release_cached(CachedPlan &c)
+{
+    if (c.last) {
+        (void)hipEventSynchronize(c.last);
+        (void)hipEventDestroy(c.last);
+    }
+    bed_plan_destroy(c.plan);
+}
 }  // namespace
 
 static bed_status solve(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
@@ -299,22 +321,39 @@ static bed_status solve(bed_dtype dt, int64_t batch, const int32_t *n, const voi
             return BED_OK;
         }
     }
-    bed_plan *p = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        CacheKey key{dt, std::vector<int32_t>(n, n + batch)};
-        auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
-            p = it->second;
-        } else {
-            if (stream_capturing(s))
-                return fail(BED_ERR_CAPTURE, "first bed_syevd for a new size mix during capture");
-            st = bed_plan_create(&p, dt, batch, n, nullptr, stream);
-            if (st != BED_OK) return st;
-            g_cache.emplace(std::move(key), p);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    const bool capturing = stream_capturing(s);
+    CacheKey key{dt, stream, std::vector<int32_t>(n, n + batch)};
+    CachedPlan *c = g_cache.find(key);
+    if (!c) {
+        if (capturing)
+            return fail(BED_ERR_CAPTURE, "first bed_syevd for a new size mix during capture");
+        CachedPlan fresh;
+        st = bed_plan_create(&fresh.plan, dt, batch, n, nullptr, stream);
+        if (st != BED_OK) return st;
+        hipError_t e = hipEventCreateWithFlags(&fresh.last, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            bed_plan_destroy(fresh.plan);
+            return hip_fail(e, "hipEventCreate");
         }
+        for (CachedPlan &old : g_cache.insert(key, fresh)) release_cached(old);
+        c = g_cache.find(key);
     }
-    return plan_run_impl(p, A, lambda, want_q ? Q : nullptr, info, s);
+    st = plan_run_impl(c->plan, A, lambda, want_q ? Q : nullptr, info, s);
+    if (st != BED_OK) return st;
+    if (capturing) {
+        g_cache.pin(key);
+    } else {
+        hipError_t e = hipEventRecord(c->last, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    return BED_OK;
+}
+
+extern "C" int32_t bed_cache_entries(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    return (int32_t)g_cache.size();
 }
 
 extern "C" bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,

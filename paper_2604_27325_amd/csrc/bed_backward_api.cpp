@@ -5,17 +5,43 @@
 #include <vector>
 
 #include "bed_host.hpp"
+#include "bed_lru.hpp"
 
 using namespace bed;
 
 namespace {
+// Work lists of mixed-size batches, one per (dtype, n[], stream), at most
+// BWD_CACHE_MAX of them (least recently used evicted after the event behind
+// its last launch has completed; pinned once used under graph capture).
+struct BwdKey {
+    int dt;
+    void *stream;
+    std::vector<int32_t> n;
+    bool operator<(const BwdKey &o) const
+    {
+        if (dt != o.dt) return dt < o.dt;
+        if (stream != o.stream) return stream < o.stream;
+        return n < o.n;
+    }
+};
 struct BwdPlan {
     WorkItem *d_items = nullptr;
     int count = 0;
     int nmax = 64;
+    hipEvent_t last = nullptr;
 };
+constexpr size_t BWD_CACHE_MAX = 32;
 std::mutex g_bwd_mu;
-std::map<std::pair<int, std::vector<int32_t>>, BwdPlan> g_bwd_cache;
+Lru<BwdKey, BwdPlan> g_bwd_cache(BWD_CACHE_MAX);
+
+void release_bwd(BwdPlan &p)
+{
+    if (p.last) {
+        (void)hipEventSynchronize(p.last);
+        (void)hipEventDestroy(p.last);
+    }
+    if (p.d_items) (void)hipFree(p.d_items);
+}
 }  // namespace
 
 extern "C" bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int32_t *n,
@@ -40,38 +66,43 @@ extern "C" bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int3
                                                eps, s);
         return e == hipSuccess ? BED_OK : hip_fail(e, "backward launch");
     }
-    BwdPlan p;
-    {
-        std::lock_guard<std::mutex> lk(g_bwd_mu);
-        auto key = std::make_pair((int)dt, std::vector<int32_t>(n, n + batch));
-        auto it = g_bwd_cache.find(key);
-        if (it != g_bwd_cache.end()) {
-            p = it->second;
-        } else {
-            if (stream_capturing(s))
-                return fail(BED_ERR_CAPTURE, "first backward for a new size mix during capture");
-            std::vector<WorkItem> items;
-            int64_t offA = 0, offL = 0;
-            for (int64_t b = 0; b < batch; ++b) {
-                items.push_back(WorkItem{offA, offL, n[b], (int32_t)b});
-                offA += (int64_t)n[b] * n[b];
-                offL += n[b];
-                p.nmax = std::max(p.nmax, (int)n[b]);
-            }
-            p.nmax = *std::max_element(n, n + batch);
-            p.count = (int)batch;
-            hipError_t e = hipMalloc(&p.d_items, sizeof(WorkItem) * items.size());
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
-            e = hipMemcpy(p.d_items, items.data(), sizeof(WorkItem) * items.size(),
-                          hipMemcpyHostToDevice);
-            if (e != hipSuccess) {
-                (void)hipFree(p.d_items);
-                return hip_fail(e, "hipMemcpy(work list)");
-            }
-            g_bwd_cache.emplace(std::move(key), p);
+    std::lock_guard<std::mutex> lk(g_bwd_mu);
+    const bool capturing = stream_capturing(s);
+    BwdKey key{(int)dt, stream, std::vector<int32_t>(n, n + batch)};
+    BwdPlan *p = g_bwd_cache.find(key);
+    if (!p) {
+        if (capturing)
+            return fail(BED_ERR_CAPTURE, "first backward for a new size mix during capture");
+        std::vector<WorkItem> items;
+        int64_t offA = 0, offL = 0;
+        for (int64_t b = 0; b < batch; ++b) {
+            items.push_back(WorkItem{offA, offL, n[b], (int32_t)b});
+            offA += (int64_t)n[b] * n[b];
+            offL += n[b];
         }
+        BwdPlan fresh;
+        fresh.nmax = *std::max_element(n, n + batch);
+        fresh.count = (int)batch;
+        hipError_t e = hipMalloc(&fresh.d_items, sizeof(WorkItem) * items.size());
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
+        e = hipMemcpy(fresh.d_items, items.data(), sizeof(WorkItem) * items.size(),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fresh.last, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipFree(fresh.d_items);
+            return hip_fail(e, "backward work list");
+        }
+        for (BwdPlan &old : g_bwd_cache.insert(key, fresh)) release_bwd(old);
+        p = g_bwd_cache.find(key);
     }
-    hipError_t e = launch_backward(dt, p.nmax, lambda, Q, dlambda, dQ, dA, p.d_items, p.count,
+    hipError_t e = launch_backward(dt, p->nmax, lambda, Q, dlambda, dQ, dA, p->d_items, p->count,
                                    eps, s);
-    return e == hipSuccess ? BED_OK : hip_fail(e, "backward launch");
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    if (capturing) {
+        g_bwd_cache.pin(key);
+    } else {
+        e = hipEventRecord(p->last, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    return BED_OK;
 }

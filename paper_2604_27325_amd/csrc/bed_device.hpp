@@ -56,6 +56,20 @@ __device__ __forceinline__ float f_rsqrt(float x)
 }
 __device__ __forceinline__ double f_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ double f_sqrt(double x) { return sqrt(x); }
+// binary64 hardware estimates refined by one Newton step, r' = r + r (1 - x r)
+// and y' = y (3/2 - x y^2 / 2): the relative error squares, from the
+// estimate's (at least 2^-22) to below 1e-12.  Used where binary64 arithmetic
+// only has to keep its rounding far below binary32's unit roundoff.
+__device__ __forceinline__ double d_rcp_nr(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double d_rsqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
 __device__ __forceinline__ float f_div(float a, float b) { return a * f_rcp(b); }
 __device__ __forceinline__ double f_div(double a, double b) { return a / b; }
 
@@ -270,6 +284,37 @@ template <typename T> __device__ __forceinline__ T wave_total(T x)
     x += dppm<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return bcast(x, 63);
 }
+
+// binary64 sum over the whole wave, in every lane.  A 64-bit DPP exchange
+// takes two 32-bit moves, so the four butterfly stages inside rows of 16 use
+// moves that read only valid lanes (no old value to clear), and the rows are
+// combined by the two permlane swaps, whose two outputs together hold every
+// row pair (a + b is the pair sum in every lane, so nothing is selected).
+template <int CTRL> __device__ __forceinline__ double dpp_move64(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum_all(double x)
+{
+    x += dpp_move64<0xB1>(x);   // lane ^ 1
+    x += dpp_move64<0x4E>(x);   // lane ^ 2
+    x += dpp_move64<0x141>(x);  // lane ^ 7 within 8
+    x += dpp_move64<0x140>(x);  // lane ^ 15 within 16
+    uint64_t b = (uint64_t)__double_as_longlong(x);
+    auto l16 = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+    auto h16 = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    x = __longlong_as_double((long long)(((uint64_t)h16[0] << 32) | l16[0])) +
+        __longlong_as_double((long long)(((uint64_t)h16[1] << 32) | l16[1]));
+    b = (uint64_t)__double_as_longlong(x);
+    auto l32 = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    auto h32 = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    return __longlong_as_double((long long)(((uint64_t)h32[0] << 32) | l32[0])) +
+           __longlong_as_double((long long)(((uint64_t)h32[1] << 32) | l32[1]));
+}
+__device__ __forceinline__ float wave_sum_all(float x) { return wave_total(x); }
 
 // Bits [lo, hi) of a 64-bit lane mask.
 __device__ __forceinline__ uint64_t lane_range(int lo, int hi)

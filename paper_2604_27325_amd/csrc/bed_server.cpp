@@ -2,11 +2,14 @@
 //
 // Requests (count matrices of one size n, caller-owned device buffers) are
 // admitted while the in-flight matrix count and the admitted bytes stay under
-// the configured limits.  A scheduler thread packs every admitted,
-// not-yet-launched request into one step on a free stream (up to max_step
-// matrices), uploads the step's pointer work list from pinned host memory
-// into a device buffer owned by that stream slot, launches one kernel per size
-// class and records an event.  Steps on different streams overlap on the
+// the configured limits (bed_admit.hpp).  At admission an event is recorded on
+// the caller's stream, so the step that reads a request's A first waits for
+// the work the caller enqueued before submitting (the kernel or copy that
+// produced A).  A scheduler thread packs every admitted, not-yet-launched
+// request into one step on a free stream (up to max_step matrices), uploads
+// the step's pointer work list from pinned host memory into a device buffer
+// owned by that stream slot, launches one kernel per size class and records
+// an event.  Steps on different streams overlap on the
 // device; completion is observed by polling the events.  The per-matrix
 // kernel configuration depends only on (n, dtype), so each request's result is
 // bitwise the same alone or in any mix.
@@ -19,6 +22,7 @@
 #include <thread>
 #include <vector>
 
+#include "bed_admit.hpp"
 #include "bed_host.hpp"
 
 using namespace bed;
@@ -35,6 +39,7 @@ struct Request {
     void *lam, *Q;
     int32_t *info;
     int64_t bytes;
+    hipEvent_t ready;  // recorded on the caller's stream at submission
     Clock::time_point t_submit;
     bool launched = false, done = false;
     double latency_us = 0.0;
@@ -58,8 +63,9 @@ struct bed_server {
     std::condition_variable cv, cv_done;
     std::deque<uint64_t> pending;
     std::map<uint64_t, Request> reqs;
+    std::vector<hipEvent_t> free_events;  // recycled readiness events
     uint64_t next_ticket = 1;
-    int64_t inflight_mats = 0, inflight_bytes = 0;
+    Admission adm;
     bool stop = false;
     std::thread worker;
     int device = 0;
@@ -84,8 +90,9 @@ static void server_loop(bed_server *s)
                     r.done = true;
                     r.latency_us =
                         std::chrono::duration<double, std::micro>(now - r.t_submit).count();
-                    s->inflight_mats -= r.count;
-                    s->inflight_bytes -= r.bytes;
+                    s->adm.release(r.count, r.bytes);
+                    s->free_events.push_back(r.ready);
+                    r.ready = nullptr;
                 }
                 sl.tickets.clear();
                 sl.busy = false;
@@ -123,6 +130,10 @@ static void server_loop(bed_server *s)
                 r.launched = true;
                 sl.tickets.push_back(tk);
             }
+            // every request's input is complete on its producer stream first
+            hipError_t e = hipSuccess;
+            for (uint64_t tk : sl.tickets)
+                if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream, s->reqs[tk].ready, 0);
             // stage the list in pinned memory grouped by (dtype, class)
             int off = 0;
             struct Launch {
@@ -138,8 +149,9 @@ static void server_loop(bed_server *s)
                     launches.push_back(Launch{d ? BED_F64 : BED_F32, c, off, (int)v.size()});
                     off += (int)v.size();
                 }
-            hipError_t e = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(PtrItem) * off,
-                                          hipMemcpyHostToDevice, sl.stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(PtrItem) * off,
+                                   hipMemcpyHostToDevice, sl.stream);
             const bed_tune dflt = default_tune();
             for (const Launch &L : launches)
                 if (e == hipSuccess)
@@ -177,6 +189,8 @@ extern "C" bed_status bed_server_create(bed_server **out, const bed_server_opts 
     auto *s = new (std::nothrow) bed_server();
     if (!s) return fail(BED_ERR_NOMEM, "host allocation failed");
     s->opts = opts;
+    s->adm.max_mats = opts.max_inflight;
+    s->adm.max_bytes = opts.mem_budget;
     s->device = opts.device;
     if (hipSetDevice(s->device) != hipSuccess) {
         delete s;
@@ -201,7 +215,7 @@ extern "C" bed_status bed_server_create(bed_server **out, const bed_server_opts 
 
 extern "C" bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t count, int32_t n,
                                         const void *A, void *lambda, void *Q, int32_t *info,
-                                        uint64_t *ticket)
+                                        void *stream, uint64_t *ticket)
 {
     if (!s || !ticket) return fail(BED_ERR_INVALID_ARG, "NULL argument");
     if (count < 1) return fail(BED_ERR_INVALID_ARG, "count < 1");
@@ -212,12 +226,31 @@ extern "C" bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t cou
     if ((st = check_ptr(A, dt, "A", false)) != BED_OK) return st;
     if ((st = check_ptr(lambda, dt, "lambda", false)) != BED_OK) return st;
     if ((st = check_ptr(Q, dt, "Q", false)) != BED_OK) return st;
-    const int64_t bytes = (int64_t)count * (2 * (int64_t)n * n + n) * (int64_t)dtype_size(dt);
+    const int64_t bytes = request_bytes(count, n, dtype_size(dt));
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->opts.max_inflight > 0 && s->inflight_mats + count > s->opts.max_inflight)
+    hipEvent_t ev = nullptr;
+    if (!s->free_events.empty()) {
+        ev = s->free_events.back();
+        s->free_events.pop_back();
+    } else {
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    switch (s->adm.admit(count, bytes)) {
+    case ADMIT_OK: break;
+    case ADMIT_INFLIGHT:
+        s->free_events.push_back(ev);
         return fail(BED_ERR_BUSY, "in-flight matrix limit reached");
-    if (s->opts.mem_budget > 0 && s->inflight_bytes + bytes > s->opts.mem_budget)
+    case ADMIT_MEMORY:
+        s->free_events.push_back(ev);
         return fail(BED_ERR_BUSY, "memory budget reached");
+    }
+    hipError_t e = hipEventRecord(ev, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        s->adm.release(count, bytes);
+        s->free_events.push_back(ev);
+        return hip_fail(e, "hipEventRecord on the submitting stream");
+    }
     Request r;
     r.ticket = s->next_ticket++;
     r.dt = dt;
@@ -228,9 +261,8 @@ extern "C" bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t cou
     r.Q = Q;
     r.info = info;
     r.bytes = bytes;
+    r.ready = ev;
     r.t_submit = Clock::now();
-    s->inflight_mats += count;
-    s->inflight_bytes += bytes;
     s->reqs.emplace(r.ticket, r);
     s->pending.push_back(r.ticket);
     *ticket = r.ticket;
@@ -257,7 +289,7 @@ extern "C" bed_status bed_server_drain(bed_server *s)
 {
     if (!s) return fail(BED_ERR_INVALID_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] { return s->inflight_mats == 0 || !s->error.empty(); });
+    s->cv_done.wait(lk, [&] { return s->adm.idle() || !s->error.empty(); });
     if (!s->error.empty()) return fail(BED_ERR_HIP, "server: %s", s->error.c_str());
     return BED_OK;
 }
@@ -271,6 +303,9 @@ extern "C" void bed_server_destroy(bed_server *s)
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    for (auto &kv : s->reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     for (auto &sl : s->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);

@@ -35,6 +35,11 @@
 #ifndef BED_ROOT
 #define BED_ROOT(depth, root, evals, reason) ((void)0)
 #endif
+// Householder step markers (a profiling build may timestamp the sub-steps of
+// one chosen step k; `wave` and `lane` are in scope where they are used).
+#ifndef BED_HSTEP
+#define BED_HSTEP(k, id) ((void)0)
+#endif
 
 namespace bed {
 
@@ -61,6 +66,17 @@ constexpr int QH_SYNC = 4;
 
 constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
 
+// Arithmetic type of the Householder reduction.  Its rounding errors are a
+// backward error of A, which the eigenvalue differences and the eigenvectors
+// of close pairs amplify by 1/gap (the backward of the decomposition divides
+// by those differences).  In binary64 -- whose FMA issues at the rate of
+// unpacked binary32 on gfx950 -- they stay far below binary32's unit
+// roundoff; T, the reflectors and tau are then rounded once to the storage
+// type.
+template <typename T> struct HhArith {
+    using type = double;
+};
+
 template <typename T, int NMAX, int NT>
 struct Smem {
     static constexpr int LD = NMAX + 1;  // odd row stride: column walks hit distinct banks
@@ -77,12 +93,14 @@ struct Smem {
     alignas(16) T Vt[NMAX * VLD];
     T a[NMAX], b[NMAX], tau[NMAX];
     T lam0[NMAX], lam1[NMAX];
+    using H = typename HhArith<T>::type;
+    static constexpr int HW = HH_WAVES<T, NMAX, NT>::value;
     union {
-        struct {  // Householder
-            T part[2 * G * NMAX];
-            T colb[2 * NMAX];
-            alignas(16) T vbuf[NW * NMAX];
-            alignas(16) T wbuf[NW * NMAX];
+        struct {  // Householder (reducing waves only, in the reduction's type)
+            H part[2 * HW * NMAX];
+            H colb[2 * NMAX];
+            alignas(16) H vbuf[HW * NMAX];
+            alignas(16) H wbuf[HW * NMAX];
         } h;
         struct {  // merges; arrays indexed by global position (node-local at [lo, hi))
             T sd[NMAX], sz[NMAX];     // sorted poles / weights (deflation in place)
@@ -155,22 +173,20 @@ __device__ __forceinline__ int node_index(int e, int d, int n) { return (((e + 1
 // [a_pp a_pq; a_pq a_qq] (Rutishauser's form): t = tan(phi) with
 // th = (a_qq - a_pp) / (2 a_pq), t = sgn(th) / (|th| + sqrt(th^2 + 1)),
 // c = 1/sqrt(1 + t^2), s = t c.  Then a_pp' = a_pp - t a_pq, a_qq' = a_qq + t a_pq.
+// Written without the quotient th: with d = a_qq - a_pp (sgn 0 = +1),
+// t = sgn(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)), whose denominator is at
+// least 2|a_pq|.  The reciprocal and 1/sqrt are refined to about one ulp, so
+// that c^2 + s^2 = 1 and the rotation is orthogonal to the working precision.
 template <typename T>
 __device__ __forceinline__ void jacobi_rot(const T app, const T aqq, const T apq, T& c, T& s, T& t)
 {
-    T tt, cc;
-    if constexpr (sizeof(T) == 4) {
-        // hardware reciprocal (rcp(inf) = 0: a huge |th| gives t = 0, the
-        // rotation's limit) and square root; c^2 + s^2 = 1 to a few ulps
-        const T th = (aqq - app) * f_rcp_fast(T(2) * apq);
-        tt = (th < T(0) ? T(-1) : T(1)) * f_rcp_fast(f_abs(th) + f_sqrt(fma(th, th, T(1))));
-        cc = f_rcp_fast(f_sqrt(fma(tt, tt, T(1))));
-    } else {
-        const T th = (aqq - app) / (T(2) * apq);
-        tt = (th < T(0) ? T(-1) : T(1)) / (f_abs(th) + f_hypot(T(1), th));
-        cc = T(1) / f_hypot(T(1), tt);
-    }
-    const bool rot = apq != T(0);  // (a NaN from a zero a_pq is selected away)
+    const T d = aqq - app;
+    const T ap2 = T(2) * apq;
+    const T den = f_abs(d) + f_sqrt(fma(d, d, ap2 * ap2));
+    // no rotation for a zero (or vanishing) a_pq: the block is already diagonal
+    const bool rot = apq != T(0) && den > T(sizeof(T) == 4 ? 1e-30f : 1e-290);
+    const T tt = (d < T(0) ? -ap2 : ap2) * f_rcp(rot ? den : T(1));
+    const T cc = f_rsqrt(fma(tt, tt, T(1)));
     t = rot ? tt : T(0);
     c = rot ? cc : T(1);
     s = rot ? tt * cc : T(0);
@@ -527,13 +543,19 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
             const T mid = T(0.5) * (L2 + U2);
             const T hn = okh ? hh : (okm ? hm : mid);
             const bool step = !(conv || tight) && hn != h;
+            // A root that meets the stopping bound still takes the Halley
+            // step from its last evaluation when that step stays in the
+            // bracket: the bound allows |f| up to 8u(1 + rho sum|z^2/delta|),
+            // and the step (third order from there) brings the root to the
+            // rounding level of f at no further evaluation.
+            const bool fin = conv && okh;
             const int nh = nhal + 1;
             const bool cap = step && nh >= SEC_CAP;
             const bool act = !done;
             U = act ? U2 : U;
             L = act ? L2 : L;
             why = act ? (f == T(0) ? 1 : (conv ? 2 : (tight ? 3 : (!step ? 4 : (cap ? 5 : 0))))) : why;
-            h = (act && step) ? hn : h;
+            h = (act && (step || fin)) ? hn : h;
             nhal = act ? nh : nhal;
             capped = act ? cap : capped;
             done = done || !step || cap;
@@ -757,31 +779,40 @@ template <typename T>
 struct HhRefl {
     T alpha, tau, rv0;
 };
-template <typename T>
-__device__ __forceinline__ HhRefl<T> hh_reflector(const T x0, const T sig)
+template <typename T, typename H>
+__device__ __forceinline__ HhRefl<H> hh_reflector(const H x0, const H sig)
 {
     // alpha = -sgn(x0) mu, mu = ||x||; v = (1, x_2.. / (x0 - alpha)) with
     // x0 - alpha = sgn(x0)(|x0| + mu); tau = (mu + |x0|)/mu = 2/(v^T v) in
     // exact arithmetic.  Two independent reciprocals (1/mu, 1/(|x0| + mu)).
     // tau = 0 when the sub-column is already zero.
-    const bool z = (sig == T(0));
-    const T s2 = fma(x0, x0, sig);
-    const T rmu = f_rsqrt(s2);
-    const T mu = s2 * rmu;
-    const T ax = f_abs(x0);
-    const T sg = (x0 < T(0)) ? T(-1) : T(1);
-    HhRefl<T> h;
+    // (binary64 arithmetic for binary32 storage: hardware estimates with one
+    // Newton step, far more accurate than the binary32 result needs; binary64
+    // storage: IEEE operations)
+    constexpr bool est = sizeof(T) < sizeof(H);
+    const bool z = (sig == H(0));
+    const H s2 = fma(x0, x0, sig);
+    const H rmu = est ? d_rsqrt_nr(s2) : f_rsqrt(s2);
+    const H mu = s2 * rmu;
+    const H ax = f_abs(x0);
+    const H sg = (x0 < H(0)) ? H(-1) : H(1);
+    HhRefl<H> h;
     h.alpha = z ? x0 : -sg * mu;
-    h.rv0 = z ? T(1) : sg * f_rcp(ax + mu);
-    h.tau = z ? T(0) : fma(ax, rmu, T(1));
+    h.rv0 = z ? H(1) : sg * (est ? d_rcp_nr(ax + mu) : f_rcp(ax + mu));
+    h.tau = z ? H(0) : fma(ax, rmu, H(1));
     return h;
 }
 
 template <typename T, int NMAX, int NT, int HW, int Q0>
 __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, const int lane,
-                                         const int wave, T (&ar)[NMAX * NMAX / (64 * HW)], T& xr,
-                                         T& sig, T& vr, T& tauk)
+                                         const int wave,
+                                         typename HhArith<T>::type (&ar)[NMAX * NMAX / (64 * HW)],
+                                         typename HhArith<T>::type& xr,
+                                         typename HhArith<T>::type& sig,
+                                         typename HhArith<T>::type& vr,
+                                         typename HhArith<T>::type& tauk)
 {
+    using H = typename HhArith<T>::type;
     constexpr int GW = 64 / NMAX;   // column groups per wave
     constexpr int G = HW * GW;      // column groups of the team
     constexpr int CPT = NMAX / G;
@@ -790,8 +821,8 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
     const int glast = wave * GW + GW - 1;  // last group of this wave
     const bool g0 = gl == 0;
     const int pos_r = (r % G) * CPT + r / G;
-    T* vb = S.u.h.vbuf + wave * NMAX;
-    T* wb = S.u.h.wbuf + wave * NMAX;
+    H* vb = S.u.h.vbuf + wave * NMAX;
+    H* wb = S.u.h.wbuf + wave * NMAX;
     // instance Q0 = NCH: every column of this wave is dead, but the wave
     // keeps stepping (barriers, pivot column, next reflector) until n - 2
     const int kb = (Q0 == 0) ? 0 : glast + G * (4 * Q0 - 1);
@@ -800,10 +831,11 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
     // k; ar holds the matrix after steps < k
     for (int k = kb; k < ke; ++k) {
         wave_sync();
-        T vc[CPT];
+        BED_HSTEP(k, 0);
+        H vc[CPT];
 #pragma unroll
         for (int j = 4 * Q0; j < CPT; ++j) vc[j] = vb[g * CPT + j];
-        T pp0 = T(0), pp1 = T(0);
+        H pp0 = H(0), pp1 = H(0);
 #pragma unroll
         for (int q = Q0; q < NCH; ++q) {
             pp0 = fma(ar[4 * q + 0], vc[4 * q + 0], pp0);
@@ -811,68 +843,81 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
             pp0 = fma(ar[4 * q + 2], vc[4 * q + 2], pp0);
             pp1 = fma(ar[4 * q + 3], vc[4 * q + 3], pp1);
         }
-        T pr = pp0 + pp1;
+        H pr = pp0 + pp1;
         if constexpr (GW >= 4) pr += xmove<16>(pr, lane);
         if constexpr (GW >= 2) pr += xmove<32>(pr, lane);
+        BED_HSTEP(k, 1);
         // pivot column k + 1 before this step's update, from its owner group;
         // in this instance its register index lies in [4 Q0, 4 Q0 + 4)
         const int c1 = k + 1;
         const int g1 = c1 % G;
-        T a1 = T(0);  // valid in group g1 (never this wave in instance NCH)
+        H a1 = H(0);  // valid in group g1 (never this wave in instance NCH)
         if constexpr (Q0 < NCH) a1 = pick<4>(ar + 4 * Q0, (c1 / G) & 3);
-        T cb;
+        H cb;
         if constexpr (HW > 1) {
-            T* pa = S.u.h.part + (k & 1) * HW * NMAX;
+            H* pa = S.u.h.part + (k & 1) * HW * NMAX;
             if (g0) pa[wave * NMAX + r] = pr;
             if (g == g1) S.u.h.colb[(k & 1) * NMAX + r] = a1;
             team_sync<NT>();
-            pr = T(0);
+            H q[HW];
 #pragma unroll
-            for (int w2 = 0; w2 < HW; ++w2) pr += pa[w2 * NMAX + r];
+            for (int w2 = 0; w2 < HW; ++w2) q[w2] = pa[w2 * NMAX + r];
+#pragma unroll
+            for (int st = 1; st < HW; st *= 2)  // pairwise (tree) sum
+#pragma unroll
+                for (int w2 = 0; w2 + st < HW; w2 += 2 * st) q[w2] += q[w2 + st];
+            pr = q[0];
             cb = S.u.h.colb[(k & 1) * NMAX + r];
+            BED_HSTEP(k, 2);
         } else {
             cb = a1;
             if constexpr (GW == 2) {
-                const T o32 = xmove<32>(a1, lane);
+                const H o32 = xmove<32>(a1, lane);
                 cb = (g == g1) ? a1 : o32;
             } else if constexpr (GW == 4) {
-                const T o16 = xmove<16>(a1, lane);
-                const T o32 = xmove<32>(a1, lane);
-                const T o48 = xmove<32>(o16, lane);
+                const H o16 = xmove<16>(a1, lane);
+                const H o32 = xmove<32>(a1, lane);
+                const H o48 = xmove<32>(o16, lane);
                 const int dd = g ^ g1;
                 cb = dd == 0 ? a1 : (dd == 1 ? o16 : (dd == 2 ? o32 : o48));
             }
         }
         pr *= tauk;
-        const T pv = wave_total(g0 ? pr * vr : T(0));
-        const T wr = pr - T(0.5) * tauk * pv * vr;
+        const H pv = wave_sum_all(g0 ? pr * vr : H(0));
+        BED_HSTEP(k, 3);
+        const H wr = pr - H(0.5) * tauk * pv * vr;
         if (g0) wb[pos_r] = wr;
         // v and w at column k + 1 are the values of row k + 1
-        const T v1 = bcast(vr, k + 1), w1 = bcast(wr, k + 1);
+        const H v1 = bcast(vr, k + 1), w1 = bcast(wr, k + 1);
         wave_sync();
-        T wc[CPT];
+        H wc[CPT];
 #pragma unroll
         for (int j = 4 * Q0; j < CPT; ++j) wc[j] = wb[g * CPT + j];
-        const T xn = fma(-wr, v1, fma(-vr, w1, cb));  // pivot column k + 1, row r
-        const T sn = wave_total((g0 && r > k + 2) ? xn * xn : T(0));
+        BED_HSTEP(k, 4);
+        const H xn = fma(-wr, v1, fma(-vr, w1, cb));  // pivot column k + 1, row r
+        const H sn = wave_sum_all((g0 && r > k + 2) ? xn * xn : H(0));
+        BED_HSTEP(k, 5);
         // reflector of step k + 1 (harmless past the last step: nothing reads
         // reflector n - 2, and b[n - 2], a[n - 2] are rewritten afterwards)
-        const HhRefl<T> h = hh_reflector(bcast(xn, k + 2), sn);
-        const T vn = (r == k + 2) ? T(1) : ((r > k + 2 && sn != T(0)) ? xn * h.rv0 : T(0));
+        const HhRefl<H> h = hh_reflector<T>(bcast(xn, k + 2), sn);
+        const H vn = (r == k + 2) ? H(1) : ((r > k + 2 && sn != H(0)) ? xn * h.rv0 : H(0));
+        BED_HSTEP(k, 6);
         if (wave == 0 && lane == 0) {
-            S.tau[k + 1] = h.tau;
-            S.b[k + 1] = h.alpha;
+            S.tau[k + 1] = T(h.tau);
+            S.b[k + 1] = T(h.alpha);
         }
         if (g0) {
             if (wave == 0) {
-                if (r == k + 1) S.a[k + 1] = xn;
-                S.Vt[(k + 1) * Smem<T, NMAX, NT>::VLD + r] = vn;
+                if (r == k + 1) S.a[k + 1] = T(xn);
+                S.Vt[(k + 1) * Smem<T, NMAX, NT>::VLD + r] = T(vn);
             }
             vb[pos_r] = vn;
         }
+        BED_HSTEP(k, 7);
         // rank-2 update of step k
 #pragma unroll
         for (int j = 4 * Q0; j < CPT; ++j) ar[j] = fma(-wr, vc[j], fma(-vr, wc[j], ar[j]));
+        BED_HSTEP(k, 8);
         xr = xn;
         sig = sn;
         vr = vn;
@@ -979,38 +1024,40 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
     // The reduction is one dependent chain; its waves issue ahead of the
     // accumulating waves that share their SIMDs.
     if constexpr (AW > 0) __builtin_amdgcn_s_setprio(1);
+    using H = typename HhArith<T>::type;
     const int r = lane % NMAX, gl = lane / NMAX, g = wave * GW + gl;
     const bool g0 = gl == 0;
-    T ar[CPT];
+    const H hs = H(sc);  // exact power of two
+    H ar[CPT];
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
         const int c = g + G * j;
-        ar[j] = (r < n && c < n) ? sc * (c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : T(0);
+        ar[j] = (r < n && c < n) ? hs * H(c <= r ? S.M[r * LD + c] : S.M[c * LD + r]) : H(0);
     }
-    T xr = (r < n) ? sc * S.M[r * LD] : T(0);  // pivot column 0 (lower triangle)
-    T sig = wave_total((g0 && r > 1) ? xr * xr : T(0));
+    H xr = (r < n) ? hs * H(S.M[r * LD]) : H(0);  // pivot column 0 (lower triangle)
+    H sig = wave_total((g0 && r > 1) ? xr * xr : H(0));
     // reflector of step 0 (harmless when n <= 2, as above)
-    const HhRefl<T> h = hh_reflector(bcast(xr, 1), sig);
-    T vr = (r == 1) ? T(1) : ((r > 1 && sig != T(0)) ? xr * h.rv0 : T(0));
-    T tauk = h.tau;
+    const HhRefl<H> h = hh_reflector<T>(bcast(xr, 1), sig);
+    H vr = (r == 1) ? H(1) : ((r > 1 && sig != H(0)) ? xr * h.rv0 : H(0));
+    H tauk = h.tau;
     if (wave == 0 && lane == 0) {
-        S.tau[0] = h.tau;
-        S.b[0] = h.alpha;
+        S.tau[0] = T(h.tau);
+        S.b[0] = T(h.alpha);
     }
     if (g0) {
         if (wave == 0) {
-            if (r == 0) S.a[0] = xr;
-            S.Vt[r] = vr;
+            if (r == 0) S.a[0] = T(xr);
+            S.Vt[r] = T(vr);
         }
         S.u.h.vbuf[wave * NMAX + (r % G) * CPT + r / G] = vr;
     }
     hh_range<T, NMAX, NT, HW, 0>(S, n, lane, wave, ar, xr, sig, vr, tauk);
     wave_sync();
     if (wave == 0 && g0 && n >= 2) {
-        if (r == n - 2) S.a[n - 2] = xr;
-        if (r == n - 1) S.b[n - 2] = xr;
+        if (r == n - 2) S.a[n - 2] = T(xr);
+        if (r == n - 1) S.b[n - 2] = T(xr);
     }
-    if (g == (n - 1) % G && r == n - 1) S.a[n - 1] = pick<CPT>(ar, (n - 1) / G);
+    if (g == (n - 1) % G && r == n - 1) S.a[n - 1] = T(pick<CPT>(ar, (n - 1) / G));
     if constexpr (AW > 0) __builtin_amdgcn_s_setprio(0);
     return 0;
 }

@@ -161,3 +161,23 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
     if (out) *out = best;
     return BED_OK;
 }
+
+extern "C" bed_status bed_tune_set(bed_dtype dt, int64_t batch, const int32_t *n,
+                                   const bed_tune *tune)
+{
+    bed_status st = check_sizes(dt, batch, n);
+    if (st != BED_OK) return st;
+    if (!tune) return fail(BED_ERR_INVALID_ARG, "tune is NULL");
+    bed_tune t = *tune;
+    const bed_tune dflt = default_tune();
+    if (t.threads_big == 0) t.threads_big = dflt.threads_big;
+    if (t.threads_mid == 0) t.threads_mid = dflt.threads_mid;
+    if (!team_supported(dt, TeamShape{64, t.threads_big}) ||
+        !team_supported(dt, TeamShape{32, t.threads_mid}))
+        return fail(BED_ERR_INVALID_ARG, "unsupported thread counts (%d, %d)", t.threads_big,
+                    t.threads_mid);
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_file_locked();
+    g_tuned[tune_key(dt, batch, n)] = t;
+    return BED_OK;
+}

@@ -81,3 +81,18 @@ def test_binding_fails_loudly_without_gpu_tensors():
         pytest.skip("host-only check")
     with pytest.raises((ValueError, RuntimeError)):
         bed.syevd(torch.eye(4))
+
+
+def test_probe_library_exports_its_header():
+    """The instrumented measurement copy (include/bed_probe.h) is its own library."""
+    probe_h = os.path.join(ROOT, "include", "bed_probe.h")
+    probe_so = os.path.join(ROOT, "paper_2604_27325_amd", "_lib", "libbed_probe.so")
+    if not os.path.exists(probe_so):
+        from paper_2604_27325_amd import build
+        build.build()
+    text = re.sub(r"/\*.*?\*/", "", open(probe_h).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(bed_[a-z_]+)\s*\(", text)))
+    assert names == ["bed_probe_phases"]
+    out = subprocess.run(["nm", "-D", "--defined-only", probe_so], capture_output=True, text=True,
+                         check=True).stdout
+    assert "bed_probe_phases" in set(re.findall(r"\sT\s(bed_\w+)", out))

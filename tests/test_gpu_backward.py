@@ -33,13 +33,14 @@ def oracle_grad_aligned(A, Q_gpu, dlam, dQ):
 
 
 def test_differentiation_workload_fp32():
-    """End to end in FP32.  F_ij = 1/(lam_j - lam_i) carries the relative error
-    of the eigenvalue differences: the FP32 divide-and-conquer leaves
-    |dlam| up to ~40 u ||A||_2 (a property of five merge levels; the binary64
-    oracle shows the same ~20-40 u against LAPACK), so with gaps >= 1e-3 and
-    ||A||_2 <= 3 single entries can move by ~1e-3.  The bulk stays at the
-    1e-5 level."""
-    A, dlam, dQ, rejected = workloads.differentiation(batch=256)
+    """End to end in FP32 on the full differentiation workload (batch 1024,
+    n = 32, eigengaps >= 1e-3), against the binary64 oracle gradient: every
+    matrix within 1e-4 (relative Frobenius).  F_ij = 1/(lam_j - lam_i) and the
+    eigenvectors of close pairs amplify the solver's backward error by 1/gap;
+    the Householder reduction runs in binary64 so that this error stays at the
+    level of rounding the result to binary32."""
+    A, dlam, dQ, rejected = workloads.differentiation()
+    assert A.shape[0] == 1024
     At = torch.from_numpy(A).to(DEV)
     lam, Q = bed.syevd(At)
     dA = bed.syevd_backward(lam, Q, torch.from_numpy(dlam).to(DEV), torch.from_numpy(dQ).to(DEV))
@@ -48,8 +49,7 @@ def test_differentiation_workload_fp32():
     ref = oracle_grad_aligned(A, Q.cpu().numpy(), dlam, dQ)
     errs = np.array([rel(dA[b], ref[b]) for b in range(A.shape[0])])
     print(f"[backward fp32] max rel {errs.max():.3g} median {np.median(errs):.3g}", flush=True)
-    assert np.median(errs) <= 1e-4
-    assert errs.max() <= 2e-3
+    assert errs.max() <= 1e-4, (int(np.argmax(errs)), errs.max())
     assert np.allclose(dA, np.swapaxes(dA, 1, 2), atol=1e-6 * np.abs(dA).max())
 
 
@@ -129,7 +129,7 @@ def test_autograd_function_end_to_end():
     ref = oracle_grad_aligned(A_np, Q.detach().cpu().numpy(), dlam, dQ)
     errs = np.array([rel(g[b], ref[b]) for b in range(32)])
     # same FP32 end-to-end bound as the differentiation workload test
-    assert np.median(errs) <= 1e-4 and errs.max() <= 2e-3
+    assert errs.max() <= 1e-4, errs.max()
 
 
 def test_packed_mixed_sizes_backward():
