@@ -93,6 +93,25 @@ typedef struct bed_plan bed_plan;
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);
 
+/* Largest batch bed_syevd_noalloc accepts. */
+#define BED_NOALLOC_MAX_BATCH 65536
+
+/* bed_syevd for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve and outputs, with no allocation, copy or memset of any kind.  A
+ * mixed-size batch's device work list is kept in a fixed array of the library
+ * (24 bytes per matrix, BED_NOALLOC_MAX_BATCH matrices, about 1.5 MiB per GPU,
+ * held until the process ends) and built by small kernels whose arguments
+ * carry the sizes; matrices of one size class run in input order, each with
+ * the kernel configuration bed_syevd uses for its size, so results equal
+ * bed_syevd's.  The array is shared by every call on a GPU and keeps the last
+ * call's list: calls that overlap in time on one GPU (different streams or
+ * threads) race and give wrong results -- serialize them.  batch >
+ * BED_NOALLOC_MAX_BATCH returns BED_ERR_INVALID_ARG; other errors as for
+ * bed_syevd.  A uniform batch needs no list and does not touch the array. */
+bed_status bed_syevd_noalloc(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
+                             void *lambda, void *Q, int32_t *info, void *stream);
+
 /* Eigenvalues only (the note computes eigenvectors "when required",
  * Sec. 2.3.5): Q is not produced; same kernel path, no Q store. */
 bed_status bed_syevals(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,

@@ -12,7 +12,7 @@ EigenDecomposition" (arXiv 2604.27325), Sec. 2.
 import ctypes
 import os
 
-__all__ = ["syevd", "syevals", "syevd_packed", "syevd_backward", "eigh", "SyevdFn", "Plan",
+__all__ = ["syevd", "syevals", "syevd_packed", "syevd_noalloc_packed", "syevd_backward", "eigh", "SyevdFn", "Plan",
            "Server", "autotune", "tune_set", "cache_entries", "BedError", "library_path",
            "load_library", "Tune"]
 
@@ -64,6 +64,7 @@ def load_library():
     vp, i64, i32p = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)
     lib.bed_syevd.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, vp]
     lib.bed_syevals.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp]
+    lib.bed_syevd_noalloc.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, vp]
     lib.bed_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64, i32p,
                                     ctypes.POINTER(Tune), vp]
     lib.bed_plan_run.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -145,6 +146,17 @@ def syevd_packed(n_list, A, lam=None, Q=None, info=None, stream=None, want_vecto
         _check(lib.bed_syevals(dt, len(n_arr), n_ptr, _dev(A, "A"), _dev(lam, "lambda"),
                                _dev(info, "info"), _stream_ptr(stream)))
     return lam, (Q if want_vectors else None), info
+
+
+def syevd_noalloc_packed(n_list, A, lam, Q, info=None, stream=None):
+    """bed_syevd_noalloc on a packed batch into caller-provided outputs (the
+    library allocates nothing; calls on one GPU must not overlap in time)."""
+    lib = load_library()
+    n_arr, n_ptr = _n_array(n_list)
+    _check(lib.bed_syevd_noalloc(_dtype_code(A.dtype), len(n_arr), n_ptr, _dev(A, "A"),
+                                 _dev(lam, "lambda"), _dev(Q, "Q"),
+                                 _dev(info, "info") if info is not None else None,
+                                 _stream_ptr(stream)))
 
 
 def syevd(A, return_info=False, stream=None):
