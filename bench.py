@@ -99,21 +99,30 @@ def profiled_traffic(name):
         return None
 
 
-def timed(torch, fn, steps, warmup, stream=None):
+def timed(torch, fn, steps, warmup, stream=None, per_step=False):
     """(wall ms per step, event ms per step) of `steps` calls of fn() after
-    `warmup` untimed ones, events on `stream` (torch's current stream if None)."""
+    `warmup` untimed ones, events on `stream` (torch's current stream if None).
+    per_step: also return the per-call event times (ms), one event pair per call."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = stream or torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step else None
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
+    for i in range(steps):
+        if per_step:
+            evs[i].record(stream)
         fn()
+    if per_step:
+        evs[steps].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
+    if per_step:
+        each = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+        return wall, e0.elapsed_time(e1) / steps, each
     return wall, e0.elapsed_time(e1) / steps
 
 
@@ -125,9 +134,10 @@ def time_solver(bed, torch, A, steps, warmup):
     info = torch.empty(b, dtype=torch.int32, device=A.device)
     flat, lflat, qflat = A.view(-1), lam.view(-1), Q.view(-1)
     nl = [n] * b
-    wall, ev = timed(torch, lambda: bed.syevd_packed(nl, flat, lam=lflat, Q=qflat, info=info),
-                     steps, warmup)
-    return wall, ev, lam, Q, info
+    wall, ev, each = timed(torch, lambda: bed.syevd_packed(nl, flat, lam=lflat, Q=qflat,
+                                                            info=info),
+                           steps, warmup, per_step=True)
+    return wall, ev, each, lam, Q, info
 
 
 def parity_sample(oracle, A_np, lam, Q, info, count=16):
@@ -143,20 +153,61 @@ def parity_sample(oracle, A_np, lam, Q, info, count=16):
             "max_orthogonality": float(worst.get("orth", 0.0))}
 
 
-def cpu_baseline(oracle, A_np, budget_s):
-    """The binary64 oracle (single thread, as committed) on a bounded sample."""
-    A64 = A_np.astype(np.float64)
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, A64, budget_s, threads):
+    """Matrices/s of the oracle over `threads` host threads (the ctypes calls
+    release the interpreter lock, so threads run the C code in parallel), one
+    16-matrix chunk of the workload per task, for about budget_s seconds."""
+    import concurrent.futures
+    import itertools
+    chunks = [A64[i:i + 16] for i in range(0, A64.shape[0], 16)]
+    it = itertools.cycle(chunks)
     done, t0 = 0, time.perf_counter()
-    while True:
-        chunk = A64[done % A64.shape[0]: done % A64.shape[0] + 16]
-        oracle.syevd(chunk)
-        done += chunk.shape[0]
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    return {"value": done / el, "unit": "eigendecomps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} matrices of the batch-512 n={A_np.shape[1]} FP32 workload "
-                      f"(promoted to FP64), {el:.1f} s single-threaded"}
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        while True:
+            batch = [next(it) for _ in range(threads)]
+            list(ex.map(oracle.syevd, batch))
+            done += sum(c.shape[0] for c in batch)
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                return done / el, done, el
+
+
+def cpu_baseline(oracle, A_np, budget_s):
+    """The binary64 oracle as committed, on the host cores of this run: all
+    cores (the reported value, cores = threads used) and one thread, each on a
+    bounded sample of the same workload; LAPACK (numpy eigh, binary64) on the
+    same matrices as context."""
+    A64 = A_np.astype(np.float64)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(avail, 16))
+    v1, d1, e1 = _oracle_rate(oracle, A64, budget_s / 2, 1)
+    vn, dn, en = _oracle_rate(oracle, A64, budget_s / 2, threads)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < 1.0:
+        np.linalg.eigh(A64[:64])
+        reps += 1
+    lapack = reps * 64 / (time.perf_counter() - t0)
+    return {"value": vn, "unit": "eigendecomps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{dn} matrices of the batch-512 n={A_np.shape[1]} FP32 workload "
+                      f"(promoted to FP64) in {en:.1f} s on {threads} threads; "
+                      f"{d1} in {e1:.1f} s on one thread",
+            "single_thread_value": v1, "nproc": os.cpu_count(), "affinity_cpus": avail,
+            "cpu_model": cpu_model(),
+            "context_numpy_eigh_binary64": lapack}
 
 
 def uneven_leg(bed, torch, steps, warmup):
@@ -182,7 +233,8 @@ def uneven_leg(bed, torch, steps, warmup):
     torch.cuda.synchronize()
     wall_g, ev_g = timed(torch, g.replay, steps, warmup)
     wall_p, ev_p = timed(torch, lambda: plan.run(A, lam, Q, info), steps, warmup)
-    # per-size plain launches on contiguous per-n buffers
+    # per-size plain launches on contiguous per-n buffers, eagerly and replayed
+    # from one graph (device work only, without the host's launch cost)
     groups = {}
     for i, n in enumerate(ns_list):
         groups.setdefault(n, []).append(mats[i])
@@ -191,12 +243,20 @@ def uneven_leg(bed, torch, steps, warmup):
         An = torch.from_numpy(np.stack(ms)).to("cuda")
         per.append((An, torch.empty(An.shape[0], n, device="cuda"), torch.empty_like(An)))
 
-    def plain():
+    def plain(stream=None):
         for An, ln, Qn in per:
             bed.syevd_packed([An.shape[1]] * An.shape[0], An.view(-1), lam=ln.view(-1),
-                             Q=Qn.view(-1))
+                             Q=Qn.view(-1), stream=stream)
 
     wall_s, ev_s = timed(torch, plain, steps, warmup)
+    with torch.cuda.stream(s):
+        plain(stream=s)
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        plain(stream=s)
+    torch.cuda.synchronize()
+    wall_sg, ev_sg = timed(torch, g2.replay, steps, warmup)
     flops = sum(flop_model(n) for n in ns_list)
     b = len(ns_list)
     return {"matrices": b, "distinct_n": len(groups), "schedule": tune,
@@ -205,7 +265,10 @@ def uneven_leg(bed, torch, steps, warmup):
             "plan_eager": {"eigendecomps_per_s": b / (wall_p * 1e-3), "ms_per_step": wall_p},
             "per_size_plain": {"eigendecomps_per_s": b / (wall_s * 1e-3), "ms_per_step": wall_s,
                                "launches": len(groups)},
-            "speedup_vs_per_size": wall_s / wall_g}
+            "per_size_plain_graph": {"eigendecomps_per_s": b / (wall_sg * 1e-3),
+                                     "ms_per_step": wall_sg, "kernel_ms": ev_sg},
+            "speedup_vs_per_size": wall_s / wall_g,
+            "speedup_vs_per_size_graph": wall_sg / wall_g}
 
 
 def backward_leg(bed, torch, steps, warmup):
@@ -327,8 +390,10 @@ def _serve_plain(bed, torch, data, arrivals):
 
 
 def serving_leg(bed, torch, requests, fracs=(0.5, 0.9), seed=5000):
-    """Saturation rate from a closed loop, then open-loop Poisson traces at
-    fractions of it, through the server and through plain sequential launches."""
+    """Saturation rates of the server and of plain sequential launches from
+    closed loops, then open-loop Poisson traces at 0.5 and 0.9 of the server's
+    rate and at 0.5 of the plain path's (a load both can sustain), each through
+    the server and through plain sequential launches."""
     from paper_2604_27325_amd import workloads
     _, counts, ns = workloads.serving_trace(seed=seed, requests=requests, qps=1.0)
     data = _ServeData(torch, counts, ns, seed + 1)
@@ -336,14 +401,20 @@ def serving_leg(bed, torch, requests, fracs=(0.5, 0.9), seed=5000):
     _serve_server(bed, data, None)  # warm-up
     el, _ = _serve_server(bed, data, None)
     r_sat = requests / el
+    el_p, _ = _serve_plain(bed, torch, data, np.zeros(requests))
+    r_plain = requests / el_p
     out = {"requests": requests, "matrices": mats, "saturation_requests_per_s": r_sat,
-           "saturation_matrices_per_s": mats / el, "loads": []}
-    for f in fracs:
-        arr, _, _ = workloads.serving_trace(seed=seed, requests=requests, qps=f * r_sat)
+           "saturation_matrices_per_s": mats / el,
+           "plain_saturation_requests_per_s": r_plain,
+           "plain_saturation_matrices_per_s": mats / el_p, "loads": []}
+    offered = [(f, f * r_sat, "server saturation") for f in fracs] + \
+        [(0.5, 0.5 * r_plain, "plain saturation")]
+    for f, qps, of in offered:
+        arr, _, _ = workloads.serving_trace(seed=seed, requests=requests, qps=qps)
         el_s, lat_s = _serve_server(bed, data, arr)
         el_p, lat_p = _serve_plain(bed, torch, data, arr)
         out["loads"].append({
-            "fraction_of_saturation": f, "qps_offered": f * r_sat,
+            "fraction_of": of, "fraction": f, "qps_offered": qps,
             "server": {"matrices_per_s": mats / el_s, "p50_ms": float(np.percentile(lat_s, 50)),
                        "p99_ms": float(np.percentile(lat_s, 99))},
             "plain_sequential": {"matrices_per_s": mats / el_p,
@@ -391,11 +462,14 @@ def main():
     for n in sizes:
         A_np, _, _ = workloads.paper_scale(n)
         A = torch.from_numpy(A_np).to("cuda")
-        wall, ev, lam, Q, info = time_solver(bed, torch, A, args.steps, args.warmup)
+        wall, ev, each, lam, Q, info = time_solver(bed, torch, A, args.steps, args.warmup)
         F = flop_model(n)
         per_n[str(n)] = {"eigendecomps_per_s": BATCH / (wall * 1e-3), "ms_per_step": wall,
                          "kernel_ms": ev, "tflops_model": BATCH * F / (ev * 1e-3) / 1e12,
-                         "flops_per_matrix": F}
+                         "flops_per_matrix": F,
+                         "launch_us_median": float(np.median(each) * 1e3),
+                         "launch_us_p10": float(np.percentile(each, 10) * 1e3),
+                         "launch_us_p90": float(np.percentile(each, 90) * 1e3)}
         print(f"[bench] n={n}: {per_n[str(n)]['eigendecomps_per_s']:.4g} matrices/s, "
               f"kernel {ev * 1e3:.1f} us", flush=True)
         if n == sizes[-1]:

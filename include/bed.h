@@ -163,6 +163,27 @@ bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int32_t *n, con
                               const void *Q, const void *dlambda, const void *dQ, void *dA,
                               double degeneracy_eps, void *stream);
 
+/* Spectral matrix functions on a decomposition (lambda, Q) as produced by
+ * bed_syevd, for the differentiable meta-layer use of Sec. 1 (matrix square
+ * root, whitening, ...):
+ *   F = Q f(Lambda) Q^T                                  (bed_spectral_apply)
+ *   dA = Q ( K o (Q^T sym(dF) Q) ) Q^T,  K_ij = (f(l_i) - f(l_j))/(l_i - l_j),
+ *        K_ii = f'(l_i)                                  (bed_spectral_backward)
+ * the first-order perturbation of f(A) (Daleckii-Krein), with every divided
+ * difference written without cancellation (e.g. 1/(sqrt l_i + sqrt l_j) for
+ * the square root, e^{l_j} expm1(l_i - l_j)/(l_i - l_j) for exp).  f is one of
+ * bed_fn; `param` is the exponent p of BED_FN_POW (ignored otherwise).  SQRT
+ * needs lambda >= 0, INVSQRT, LOG and POW need lambda > 0 (otherwise the
+ * IEEE result of the function, NaN or infinity, propagates).  F, dF, dA have
+ * A's packed layout; dA is symmetric.  Errors as for bed_syevd_backward. */
+typedef enum { BED_FN_SQRT = 0, BED_FN_INVSQRT = 1, BED_FN_EXP = 2, BED_FN_LOG = 3,
+               BED_FN_POW = 4 } bed_fn;
+bed_status bed_spectral_apply(bed_dtype dt, int64_t batch, const int32_t *n, const void *lambda,
+                              const void *Q, int32_t fn, double param, void *F, void *stream);
+bed_status bed_spectral_backward(bed_dtype dt, int64_t batch, const int32_t *n,
+                                 const void *lambda, const void *Q, int32_t fn, double param,
+                                 const void *dF, void *dA, void *stream);
+
 /* Serving: continuous batching of eigendecomposition requests.
  *   streams      device streams the server launches on (1..16)
  *   max_inflight matrices admitted but not yet completed (0 = unlimited)

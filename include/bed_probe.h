@@ -33,13 +33,16 @@ extern "C" {
  *                     7 v broadcast writes, 8 rank-2 update, 9 a
  *                     second stamp right after 8 (the cost of one marker,
  *                     which waits for outstanding LDS and scalar operations).
- * marks and steps are device arrays of batch*64 and batch*16 int64 values;
- * they are cleared first.  Synchronizes `stream` before the launch (the
+ *   defl[b*2 + t]     (may be NULL) deflations of team b summed over its merge
+ *                     depths: t = 0 type 1 (rho |z_i| <= tol), t = 1 type 2
+ *                     (Givens rotation of a close pair of poles).
+ * marks, steps and defl are device arrays of batch*64, batch*16 and batch*2
+ * int64 values; they are cleared first.  Synchronizes `stream` before the launch (the
  * buffer addresses are copied from host locals).  Returns 0 on success, 1 for
  * an invalid argument, 3 for a HIP failure. */
 int32_t bed_probe_phases(int32_t dtype, int32_t threads, int32_t n, int64_t batch,
                          const void *A, void *lambda, void *Q, long long *marks,
-                         long long *steps, void *stream);
+                         long long *steps, long long *defl, void *stream);
 
 #ifdef __cplusplus
 }

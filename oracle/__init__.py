@@ -202,3 +202,58 @@ def syevd_backward(lam, Q, dlam=None, dQ=None, eps=1e3 * 2.0 ** -53):
                                _ptr(dq) if dq is not None else None, float(eps), _ptr(out))
         dA[i] = out
     return dA[0] if single else dA
+
+
+# ---------------------------------------------------------------------------
+# Spectral matrix functions (the differentiable meta-layer use of Sec. 1):
+# plain binary64 definitions on a given decomposition A = Q diag(lam) Q^T.
+# ---------------------------------------------------------------------------
+def _fn_value(fn, x, p):
+    if fn == "sqrt":
+        return np.sqrt(x)
+    if fn == "invsqrt":
+        return 1.0 / np.sqrt(x)
+    if fn == "exp":
+        return np.exp(x)
+    if fn == "log":
+        return np.log(x)
+    if fn == "pow":
+        return x ** p
+    raise ValueError(fn)
+
+
+def _fn_deriv(fn, x, p):
+    if fn == "sqrt":
+        return 0.5 / np.sqrt(x)
+    if fn == "invsqrt":
+        return -0.5 * x ** -1.5
+    if fn == "exp":
+        return np.exp(x)
+    if fn == "log":
+        return 1.0 / x
+    if fn == "pow":
+        return p * x ** (p - 1.0)
+    raise ValueError(fn)
+
+
+def spectral_apply(lam, Q, fn, p=0.0):
+    """F = Q f(Lambda) Q^T, the definition, for one matrix or a batch."""
+    lam, Q = _d(lam), _d(Q)
+    f = _fn_value(fn, lam, p)
+    return np.einsum("...ik,...k,...jk->...ij", Q, f, Q)
+
+
+def spectral_backward(lam, Q, dF, fn, p=0.0):
+    """dA = Q (K o Q^T sym(dF) Q) Q^T with K_ij = (f(l_i) - f(l_j))/(l_i - l_j)
+    and K_ij = f'(l_i) where l_i == l_j (first-order perturbation of f(A),
+    Daleckii-Krein), plain divided differences, one matrix or a batch."""
+    lam, Q, dF = _d(lam), _d(Q), _d(dF)
+    f = _fn_value(fn, lam, p)
+    li, lj = lam[..., :, None], lam[..., None, :]
+    d = li - lj
+    eq = d == 0.0
+    K = np.where(eq, _fn_deriv(fn, np.broadcast_to(li, d.shape), p),
+                 (f[..., :, None] - f[..., None, :]) / np.where(eq, 1.0, d))
+    S = 0.5 * (dF + np.swapaxes(dF, -1, -2))
+    W = np.swapaxes(Q, -1, -2) @ S @ Q
+    return Q @ (K * W) @ np.swapaxes(Q, -1, -2)

@@ -12,7 +12,8 @@ EigenDecomposition" (arXiv 2604.27325), Sec. 2.
 import ctypes
 import os
 
-__all__ = ["syevd", "syevals", "syevd_packed", "syevd_noalloc_packed", "syevd_backward", "eigh", "SyevdFn", "Plan",
+__all__ = ["syevd", "syevals", "syevd_packed", "syevd_noalloc_packed", "spectral_apply",
+           "spectral_backward", "matrix_function", "FUNCTIONS", "syevd_backward", "eigh", "SyevdFn", "Plan",
            "Server", "autotune", "tune_set", "cache_entries", "BedError", "library_path",
            "load_library", "Tune"]
 
@@ -72,6 +73,10 @@ def load_library():
     lib.bed_plan_destroy.argtypes = [vp]
     lib.bed_plan_destroy.restype = None
     lib.bed_autotune.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, ctypes.POINTER(Tune)]
+    lib.bed_spectral_apply.argtypes = [ctypes.c_int, i64, i32p, vp, vp, ctypes.c_int32,
+                                       ctypes.c_double, vp, vp]
+    lib.bed_spectral_backward.argtypes = [ctypes.c_int, i64, i32p, vp, vp, ctypes.c_int32,
+                                          ctypes.c_double, vp, vp, vp]
     lib.bed_tune_set.argtypes = [ctypes.c_int, i64, i32p, ctypes.POINTER(Tune)]
     lib.bed_cache_entries.restype = ctypes.c_int32
     lib.bed_syevd_backward.argtypes = [ctypes.c_int, i64, i32p, vp, vp, vp, vp, vp,
@@ -207,6 +212,50 @@ def syevd_backward(lam, Q, dlam=None, dQ=None, eps=0.0, n_list=None, stream=None
     return dA
 
 
+FUNCTIONS = {"sqrt": 0, "invsqrt": 1, "exp": 2, "log": 3, "pow": 4}
+
+
+def _fn_code(fn):
+    if fn not in FUNCTIONS:
+        raise ValueError(f"unknown function {fn!r} (one of {sorted(FUNCTIONS)})")
+    return FUNCTIONS[fn]
+
+
+def _batch_shape(lam, Q, n_list):
+    if n_list is None:
+        b, n = (lam.shape[0] if lam.dim() == 2 else 1), lam.shape[-1]
+        n_list = [n] * b
+    return n_list
+
+
+def spectral_apply(lam, Q, fn, p=0.0, n_list=None, stream=None, out=None):
+    """F = Q f(Lambda) Q^T for a decomposition (uniform (batch, n[, n]) tensors,
+    or flat packed tensors with n_list); fn in sqrt, invsqrt, exp, log, pow."""
+    import torch
+    lib = load_library()
+    n_arr, n_ptr = _n_array(_batch_shape(lam, Q, n_list))
+    lam_c, Q_c = lam.contiguous(), Q.contiguous()
+    F = torch.empty_like(Q_c) if out is None else out
+    _check(lib.bed_spectral_apply(_dtype_code(Q.dtype), len(n_arr), n_ptr, _dev(lam_c, "lambda"),
+                                  _dev(Q_c, "Q"), _fn_code(fn), float(p), _dev(F, "F"),
+                                  _stream_ptr(stream)))
+    return F
+
+
+def spectral_backward(lam, Q, dF, fn, p=0.0, n_list=None, stream=None, out=None):
+    """dA = Q (K o Q^T sym(dF) Q) Q^T, K the divided differences of f."""
+    import torch
+    lib = load_library()
+    n_arr, n_ptr = _n_array(_batch_shape(lam, Q, n_list))
+    lam_c, Q_c, dF_c = lam.contiguous(), Q.contiguous(), dF.contiguous()
+    dA = torch.empty_like(Q_c) if out is None else out
+    _check(lib.bed_spectral_backward(_dtype_code(Q.dtype), len(n_arr), n_ptr,
+                                     _dev(lam_c, "lambda"), _dev(Q_c, "Q"), _fn_code(fn),
+                                     float(p), _dev(dF_c, "dF"), _dev(dA, "dA"),
+                                     _stream_ptr(stream)))
+    return dA
+
+
 def _make_fn():
     import torch
 
@@ -232,6 +281,30 @@ def _make_fn():
             dA = syevd_backward(l2, q2, dl, dq, eps=ctx.eps)
             return (dA[0] if single else dA), None
 
+    class MatrixFunctionFn(torch.autograd.Function):
+        """F = f(A) for symmetric A through the library: the decomposition, then
+        Q f(Lambda) Q^T; backward by the divided differences of f."""
+
+        @staticmethod
+        def forward(ctx, A, fn, p=0.0):
+            lam, Q = syevd(A)
+            ctx.save_for_backward(lam, Q)
+            ctx.fn, ctx.p = fn, p
+            single = lam.dim() == 1
+            F = spectral_apply(lam.unsqueeze(0) if single else lam,
+                               Q.unsqueeze(0) if single else Q, fn, p)
+            return F[0] if single else F
+
+        @staticmethod
+        def backward(ctx, dF):
+            lam, Q = ctx.saved_tensors
+            single = lam.dim() == 1
+            dA = spectral_backward(lam.unsqueeze(0) if single else lam,
+                                   Q.unsqueeze(0) if single else Q,
+                                   dF.unsqueeze(0) if single else dF, ctx.fn, ctx.p)
+            return (dA[0] if single else dA), None, None
+
+    SyevdFn.MatrixFunctionFn = MatrixFunctionFn
     return SyevdFn
 
 
@@ -245,6 +318,13 @@ class _LazyFn:
 
 
 SyevdFn = _LazyFn()
+
+
+def matrix_function(A, fn, p=0.0):
+    """Differentiable f(A) = Q f(Lambda) Q^T of a symmetric (batch of) GPU
+    matrix through the library; fn in sqrt, invsqrt, exp, log, pow."""
+    _fn_code(fn)
+    return SyevdFn.MatrixFunctionFn.apply(A, fn, p)
 
 
 def eigh(A, eps=0.0):

@@ -6,41 +6,38 @@
 //
 // The note motivates the solver as a differentiable meta-layer (Sec. 1); the
 // formula is the standard one for symmetric eigendecomposition.  One workgroup
-// per matrix; the three products run out of LDS.
+// per matrix; the three products run on 16x16x4 matrix-core tiles out of LDS
+// (bed_gemm.hpp).
 #include "bed_device.hpp"
+#include "bed_gemm.hpp"
 #include "bed_internal.hpp"
 
 namespace bed {
 
 template <typename T, int NMAX>
 struct BwdSmem {
-    static constexpr int LD = NMAX + 1;
-    T Q[NMAX * LD];
-    T X[NMAX * LD];  // dQ, then S
-    T Y[NMAX * LD];  // Q^T dQ, then Q S
+    static constexpr int SZ = Lds<NMAX>::SIZE;
+    T Q[SZ];
+    T X[SZ];  // dQ, then S, then dA
+    T Y[SZ];  // Q^T dQ, then Q S
     T lam[NMAX], dlam[NMAX];
     T lmax;
 };
 
+// One team per matrix: three n x n products on MFMA tiles out of LDS, with
+// the guarded F applied between the first two.
 template <typename T, int NMAX, int NT>
 __device__ __forceinline__ void bwd_team(const T *__restrict__ lam, const T *__restrict__ Q,
-                         const T *__restrict__ dlam, const T *__restrict__ dQ, T *__restrict__ dA,
-                         const int n, const T eps, BwdSmem<T, NMAX> &S, const int t)
+                                         const T *__restrict__ dlam, const T *__restrict__ dQ,
+                                         T *__restrict__ dA, const int n, const T eps,
+                                         BwdSmem<T, NMAX> &S, const int t)
 {
-    constexpr int LD = BwdSmem<T, NMAX>::LD;
-    for (int i = t / n, j = t % n, e = t; e < n * n; e += NT) {
-        S.Q[i * LD + j] = Q[e];
-        S.X[i * LD + j] = dQ ? dQ[e] : T(0);
-        j += NT % n;
-        i += NT / n;
-        if (j >= n) {
-            j -= n;
-            ++i;
-        }
-    }
-    for (int e = t; e < n; e += NT) {
-        S.lam[e] = lam[e];
-        S.dlam[e] = dlam ? dlam[e] : T(0);
+    constexpr int LD = Lds<NMAX>::LD;
+    team_load<T, NMAX, NT>(Q, S.Q, n, t);
+    team_load<T, NMAX, NT>(dQ, S.X, n, t);
+    for (int e = t; e < NMAX; e += NT) {
+        S.lam[e] = e < n ? lam[e] : T(0);
+        S.dlam[e] = (e < n && dlam) ? dlam[e] : T(0);
     }
     __syncthreads();
     if (t < 64) {
@@ -51,42 +48,31 @@ __device__ __forceinline__ void bwd_team(const T *__restrict__ lam, const T *__r
         if (t == 0) S.lmax = m;
     }
     // Y = Q^T dQ
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e / n, j = e - (e / n) * n;
-        T acc = T(0);
-        for (int r = 0; r < n; ++r) acc += S.Q[r * LD + i] * S.X[r * LD + j];
-        S.Y[i * LD + j] = acc;
-    }
+    team_gemm<T, NMAX, NT, true, false>(S.Q, S.X, S.Y, n, t);
     __syncthreads();
-    // X = diag(dlam) + sym(F o Y)
+    // X = diag(dlam) + sym(F o Y), F_ij = 1/(lam_j - lam_i) outside the guard
     const T guard = eps * f_max(T(1), S.lmax);
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e / n, j = e - (e / n) * n;
+    for (int e = t; e < NMAX * NMAX; e += NT) {
+        const int i = e / NMAX, j = e % NMAX;
         T v = T(0);
-        if (i == j) {
-            v = S.dlam[i];
-        } else {
-            const T gap = S.lam[j] - S.lam[i];
-            if (f_abs(gap) > guard) v = T(0.5) * (S.Y[i * LD + j] - S.Y[j * LD + i]) / gap;
+        if (i < n && j < n) {
+            if (i == j) {
+                v = S.dlam[i];
+            } else {
+                const T gap = S.lam[j] - S.lam[i];
+                v = f_abs(gap) > guard ? T(0.5) * f_div(S.Y[i * LD + j] - S.Y[j * LD + i], gap)
+                                       : T(0);
+            }
         }
         S.X[i * LD + j] = v;
     }
     __syncthreads();
-    // Y = Q X
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e / n, j = e - (e / n) * n;
-        T acc = T(0);
-        for (int r = 0; r < n; ++r) acc += S.Q[i * LD + r] * S.X[r * LD + j];
-        S.Y[i * LD + j] = acc;
-    }
+    // Y = Q X, then X = Y Q^T = dA
+    team_gemm<T, NMAX, NT, false, false>(S.Q, S.X, S.Y, n, t);
     __syncthreads();
-    // dA = Y Q^T
-    for (int e = t; e < n * n; e += NT) {
-        const int i = e / n, j = e - (e / n) * n;
-        T acc = T(0);
-        for (int r = 0; r < n; ++r) acc += S.Y[i * LD + r] * S.Q[j * LD + r];
-        dA[e] = acc;
-    }
+    team_gemm<T, NMAX, NT, false, true>(S.Y, S.Q, S.X, n, t);
+    __syncthreads();
+    team_store<T, NMAX, NT>(S.X, dA, n, t);
 }
 
 template <typename T, int NMAX, int NT>

@@ -1,5 +1,7 @@
-// bed_backward_api.cpp -- C ABI of the backward kernel.
+// bed_backward_api.cpp -- C ABI of the backward kernel, and the cached work
+// lists of mixed-size batches that it shares with the spectral functions.
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -44,6 +46,55 @@ void release_bwd(BwdPlan &p)
 }
 }  // namespace
 
+namespace bed {
+// Runs `launch` with the device work list (packed offsets in input order) of
+// a mixed-size batch, taken from the bounded per-stream cache (created on
+// first use, refused under capture), and records the cache entry's event
+// behind the launch (or pins the entry when the stream is being captured).
+bed_status with_worklist(bed_dtype dt, int64_t batch, const int32_t *n, hipStream_t s,
+                         const std::function<hipError_t(const WorkItem *, int, int)> &launch)
+{
+    std::lock_guard<std::mutex> lk(g_bwd_mu);
+    const bool capturing = stream_capturing(s);
+    BwdKey key{(int)dt, (void *)s, std::vector<int32_t>(n, n + batch)};
+    BwdPlan *p = g_bwd_cache.find(key);
+    if (!p) {
+        if (capturing)
+            return fail(BED_ERR_CAPTURE, "first call for a new size mix during capture");
+        std::vector<WorkItem> items;
+        int64_t offA = 0, offL = 0;
+        for (int64_t b = 0; b < batch; ++b) {
+            items.push_back(WorkItem{offA, offL, n[b], (int32_t)b});
+            offA += (int64_t)n[b] * n[b];
+            offL += n[b];
+        }
+        BwdPlan fresh;
+        fresh.nmax = *std::max_element(n, n + batch);
+        fresh.count = (int)batch;
+        hipError_t e = hipMalloc(&fresh.d_items, sizeof(WorkItem) * items.size());
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
+        e = hipMemcpy(fresh.d_items, items.data(), sizeof(WorkItem) * items.size(),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fresh.last, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipFree(fresh.d_items);
+            return hip_fail(e, "work list");
+        }
+        for (BwdPlan &old : g_bwd_cache.insert(key, fresh)) release_bwd(old);
+        p = g_bwd_cache.find(key);
+    }
+    hipError_t e = launch(p->d_items, p->count, p->nmax);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (capturing) {
+        g_bwd_cache.pin(key);
+    } else {
+        e = hipEventRecord(p->last, s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    return BED_OK;
+}
+}  // namespace bed
+
 extern "C" bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int32_t *n,
                                          const void *lambda, const void *Q, const void *dlambda,
                                          const void *dQ, void *dA, double degeneracy_eps,
@@ -66,43 +117,7 @@ extern "C" bed_status bed_syevd_backward(bed_dtype dt, int64_t batch, const int3
                                                eps, s);
         return e == hipSuccess ? BED_OK : hip_fail(e, "backward launch");
     }
-    std::lock_guard<std::mutex> lk(g_bwd_mu);
-    const bool capturing = stream_capturing(s);
-    BwdKey key{(int)dt, stream, std::vector<int32_t>(n, n + batch)};
-    BwdPlan *p = g_bwd_cache.find(key);
-    if (!p) {
-        if (capturing)
-            return fail(BED_ERR_CAPTURE, "first backward for a new size mix during capture");
-        std::vector<WorkItem> items;
-        int64_t offA = 0, offL = 0;
-        for (int64_t b = 0; b < batch; ++b) {
-            items.push_back(WorkItem{offA, offL, n[b], (int32_t)b});
-            offA += (int64_t)n[b] * n[b];
-            offL += n[b];
-        }
-        BwdPlan fresh;
-        fresh.nmax = *std::max_element(n, n + batch);
-        fresh.count = (int)batch;
-        hipError_t e = hipMalloc(&fresh.d_items, sizeof(WorkItem) * items.size());
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(work list)");
-        e = hipMemcpy(fresh.d_items, items.data(), sizeof(WorkItem) * items.size(),
-                      hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&fresh.last, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            (void)hipFree(fresh.d_items);
-            return hip_fail(e, "backward work list");
-        }
-        for (BwdPlan &old : g_bwd_cache.insert(key, fresh)) release_bwd(old);
-        p = g_bwd_cache.find(key);
-    }
-    hipError_t e = launch_backward(dt, p->nmax, lambda, Q, dlambda, dQ, dA, p->d_items, p->count,
-                                   eps, s);
-    if (e != hipSuccess) return hip_fail(e, "backward launch");
-    if (capturing) {
-        g_bwd_cache.pin(key);
-    } else {
-        e = hipEventRecord(p->last, s);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    }
-    return BED_OK;
+    return with_worklist(dt, batch, n, s, [&](const WorkItem *items, int count, int nmax) {
+        return launch_backward(dt, nmax, lambda, Q, dlambda, dQ, dA, items, count, eps, s);
+    });
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "../../include/bed.h"
 #include "bed_internal.hpp"
 
@@ -26,5 +28,10 @@ bed_tune tuned_or_default(bed_dtype dt, int64_t batch, const int32_t *n);
 
 bed_status plan_run_impl(const bed_plan *p, const void *A, void *lam, void *Q, int32_t *info,
                          hipStream_t s);
+
+// Runs `launch(items, count, nmax)` with the cached device work list of a
+// mixed-size batch (input order), recording its use on stream s.
+bed_status with_worklist(bed_dtype dt, int64_t batch, const int32_t *n, hipStream_t s,
+                         const std::function<hipError_t(const WorkItem *, int, int)> &launch);
 
 }  // namespace bed

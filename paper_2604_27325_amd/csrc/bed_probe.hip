@@ -3,6 +3,8 @@
 // syevd_team code is compiled with its phase markers defined:
 //   BED_PHASE(id)   thread 0 of each team stores the 100 MHz real-time clock
 //                   (s_memrealtime) at phase boundary id into marks[b][id];
+//   BED_DEFL(t1,t2) thread 0 adds the type-1 and type-2 deflations of each
+//                   merge depth into defl[b][0], defl[b][1];
 //   BED_HSTEP(k,id) lane 0 of wave 0 stores the shader clock (s_memtime) at
 //                   sub-step id of the middle Householder step (k = NMAX/2)
 //                   into steps[b][id]; after the last sub-step a second stamp
@@ -18,6 +20,7 @@ namespace bed {
 namespace probe {
 __device__ long long *g_marks;
 __device__ long long *g_steps;
+__device__ long long *g_defl;
 }  // namespace probe
 }  // namespace bed
 
@@ -33,6 +36,15 @@ __device__ long long *g_steps;
             long long *st_ = ::bed::probe::g_steps + (long long)blockIdx.x * BED_PROBE_SUBSTEPS; \
             st_[(id)] = (long long)clock64();                                            \
             if ((id) == 8) st_[9] = (long long)clock64(); /* marker's own cost */        \
+        }                                                                                \
+    } while (0)
+
+#define BED_DEFL(type1, type2)                                                         \
+    do {                                                                                 \
+        const int t1_ = (type1), t2_ = (type2);                                          \
+        if (::bed::probe::g_defl && threadIdx.x == 0) {                                  \
+            ::bed::probe::g_defl[2 * (long long)blockIdx.x] += t1_;                      \
+            ::bed::probe::g_defl[2 * (long long)blockIdx.x + 1] += t2_;                  \
         }                                                                                \
     } while (0)
 
@@ -75,7 +87,7 @@ static hipError_t probe_t(int nt, const void *A, int n, int64_t batch, void *lam
 
 extern "C" int32_t bed_probe_phases(int32_t dtype, int32_t threads, int32_t n, int64_t batch,
                                     const void *A, void *lambda, void *Q, long long *marks,
-                                    long long *steps, void *stream)
+                                    long long *steps, long long *defl, void *stream)
 {
     if (n < 1 || n > 64 || batch < 1 || !A || !lambda || !marks || !steps) return 1;
     hipStream_t s = (hipStream_t)stream;
@@ -87,6 +99,11 @@ extern "C" int32_t bed_probe_phases(int32_t dtype, int32_t threads, int32_t n, i
                                    hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyToSymbolAsync(HIP_SYMBOL(bed::probe::g_steps), &steps, sizeof(steps), 0,
+                                   hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && defl)
+        e = hipMemsetAsync(defl, 0, sizeof(long long) * 2 * batch, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(bed::probe::g_defl), &defl, sizeof(defl), 0,
                                    hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host values above are locals
     if (e == hipSuccess)

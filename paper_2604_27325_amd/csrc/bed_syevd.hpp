@@ -40,6 +40,11 @@
 #ifndef BED_HSTEP
 #define BED_HSTEP(k, id) ((void)0)
 #endif
+// Deflation counts of one merge depth (type 1: rho |z_i| <= tol; type 2:
+// Givens rotations), reported by lane 0 of wave 0 in a profiling build.
+#ifndef BED_DEFL
+#define BED_DEFL(type1, type2) ((void)0)
+#endif
 
 namespace bed {
 
@@ -1285,6 +1290,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             // Frobenius norm of the node (Eq. (10)), from D + rho z z^T
             const T fro2 = d2 + T(2) * rho * dz + rho * rho * zz0 * zz0;
             bool defl = act && (rho * f_abs(zp) <= tol);  // type 1
+            const int n_type1 = __popcll(__ballot(defl));
             if (defl) zp = T(0);
             // type 2 candidates against the previous non-deflated component
             const uint64_t live = __ballot(act && !defl);
@@ -1393,6 +1399,8 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             }
             const bool anyrot = __ballot(hasrot) != 0;
             if (e == 0) S.anyrot = anyrot ? 1 : 0;
+            BED_DEFL(n_type1, (int)wave_total(float(act && e == lo ? my_nrot : 0)));
+            (void)n_type1;
             BED_MARK(d, 15);
         }
         team_sync<NT>();

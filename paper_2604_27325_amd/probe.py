@@ -43,7 +43,7 @@ def run(n, threads, dtype="f32", lib_path=PROBE_LIB):
     lib = ctypes.CDLL(lib_path)
     vp = ctypes.c_void_p
     lib.bed_probe_phases.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                     ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+                                     ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
     A_np, _, _ = workloads.paper_scale(n)
     dt = torch.float32 if dtype == "f32" else torch.float64
     A = torch.from_numpy(A_np).to("cuda", dt)
@@ -52,18 +52,20 @@ def run(n, threads, dtype="f32", lib_path=PROBE_LIB):
     Q = torch.empty_like(A)
     marks = torch.zeros(b * PHASES, dtype=torch.int64, device="cuda")
     steps = torch.zeros(b * SUBSTEPS, dtype=torch.int64, device="cuda")
+    defl = torch.zeros(b * 2, dtype=torch.int64, device="cuda")
     s = torch.cuda.current_stream()
     for _ in range(3):  # warm-up, then the recorded launch
         st = lib.bed_probe_phases(0 if dtype == "f32" else 1, threads, n, b, vp(A.data_ptr()),
                                   vp(lam.data_ptr()), vp(Q.data_ptr()), vp(marks.data_ptr()),
-                                  vp(steps.data_ptr()), vp(s.cuda_stream))
+                                  vp(steps.data_ptr()), vp(defl.data_ptr()), vp(s.cuda_stream))
         if st != 0:
             raise RuntimeError(f"bed_probe_phases returned {st}")
     torch.cuda.synchronize()
-    return marks.view(b, PHASES).cpu().numpy(), steps.view(b, SUBSTEPS).cpu().numpy()
+    return (marks.view(b, PHASES).cpu().numpy(), steps.view(b, SUBSTEPS).cpu().numpy(),
+            defl.view(b, 2).cpu().numpy())
 
 
-def report(n, threads, hstep, marks, steps):
+def report(n, threads, hstep, marks, steps, defl=None):
     order = phase_names(n)
     lines = [f"phase timing, batch 512 n={n} FP32, {threads} threads per matrix "
              "(mean over teams, 100 MHz clock)", "", "| phase | mean us | max us |", "|---|---|---|"]
@@ -94,6 +96,10 @@ def report(n, threads, hstep, marks, steps):
                 prev = i
         full = float(np.mean(st[:, 8] - st[:, 0]))
         lines.append(f"| **step (start to end of update, markers included)** | {full:.0f} |")
+    if defl is not None:
+        lines += ["", f"deflations per matrix (mean over {defl.shape[0]}): type 1 "
+                  f"{defl[:, 0].mean():.2f}, type 2 {defl[:, 1].mean():.3f}; matrices with a "
+                  f"type-2 rotation: {int((defl[:, 1] > 0).sum())}"]
     return "\n".join(lines)
 
 
@@ -105,8 +111,8 @@ def main():
     a = ap.parse_args()
     threads = a.threads or (64 if a.n <= 16 else (128 if a.n <= 32 else 512))
     hstep = 8 if a.n <= 16 else (16 if a.n <= 32 else 32)
-    marks, steps = run(a.n, threads, lib_path=a.lib)
-    print(report(a.n, threads, hstep, marks, steps))
+    marks, steps, defl = run(a.n, threads, lib_path=a.lib)
+    print(report(a.n, threads, hstep, marks, steps, defl))
 
 
 if __name__ == "__main__":

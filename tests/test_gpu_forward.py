@@ -93,12 +93,20 @@ def test_in_place_and_determinism():
     assert torch.equal(lam3, lam1) and torch.equal(B, Q1)
 
 
-def test_eigenvalues_only_matches_full():
-    rng = np.random.default_rng(5)
-    A = torch.from_numpy(workloads.covariance(rng, 32, 48).astype(np.float32)).to(DEV)
-    lam, _ = bed.syevd(A)
-    lam2 = bed.syevals(A)
-    assert torch.equal(lam, lam2)
+@pytest.mark.parametrize("n", [5, 17, 32, 48, 64])
+def test_eigenvalues_only_matches_oracle(n):
+    """bed_syevals (no eigenvectors) against the oracle's eigenvalues (R1), on
+    Gaussian and covariance matrices and on the planted-pair workload."""
+    rng = np.random.default_rng(5 + n)
+    A_np = np.concatenate([workloads.gaussian_sym(rng, 16, n), workloads.covariance(rng, 16, n)])
+    if n in (32, 48, 64):
+        A_np = np.concatenate([A_np, workloads.paper_scale(n)[0][:64]])
+    A_np = A_np.astype(np.float32)
+    lam = bed.syevals(torch.from_numpy(A_np).to(DEV)).cpu().numpy()
+    lam_o, _, _ = oracle.syevd(A_np.astype(np.float64))
+    err = np.abs(lam - lam_o).max(axis=1) / np.abs(lam_o).max(axis=1)
+    print(f"[syevals n={n}] max eigenvalue error {err.max():.3g} x ||A||", flush=True)
+    assert err.max() <= 1e-5
 
 
 def test_uneven_packed_batch_matches_oracle():

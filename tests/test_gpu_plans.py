@@ -153,3 +153,87 @@ def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
     worst, fails = compare_batch(mats, lg, qg, lo, qo, npdt, info=info.cpu().numpy())
     print(f"  worst {worst}", flush=True)
     assert not fails, fails[:3]
+
+
+def test_uneven_workload_full_size_graph_matches_oracle():
+    """The whole uneven workload (4096 matrices, n ~ U{4..64}, spectra
+    log-uniform over [1e-4, 1]): autotuned schedule, plan captured in a HIP
+    graph, replayed, every matrix against the oracle."""
+    ns, mats = workloads.uneven()
+    assert len(ns) == 4096
+    ns = [int(v) for v in ns]
+    _, flat = workloads.pack(mats)
+    A = torch.from_numpy(flat).to(DEV)
+    lam = torch.empty(int(np.sum(ns)), device=DEV)
+    Q = torch.empty_like(A)
+    info = torch.zeros(len(ns), dtype=torch.int32, device=DEV)
+    tune = bed.autotune(torch.float32, ns, A, lam, Q)
+    plan = bed.Plan(torch.float32, ns, tune=tune)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.run(A, lam, Q, info, stream=s)  # warm-up on the capture stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.run(A, lam, Q, info, stream=s)
+    lam.fill_(-1.0)
+    Q.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    lg, qg = split(ns, lam.cpu().numpy(), Q.cpu().numpy())
+    lo, qo = split(ns, lam_o, Q_o)
+    worst, fails = compare_batch(mats, lg, qg, lo, qo, np.float32, info=info.cpu().numpy())
+    print(f"[uneven 4096 graph, schedule {tune}] worst {worst}", flush=True)
+    assert not fails, fails[:3]
+
+
+def test_same_mix_on_two_streams_concurrently():
+    """With a persistent schedule stored for a size mix, bed_syevd on two
+    streams at once must not share the plan's work counter: each stream's
+    result equals the oracle's and the other stream's, bit for bit."""
+    ns, mats = workloads.uneven(seed=3200, batch=700)
+    ns = [int(v) for v in ns]
+    _, flat = workloads.pack(mats)
+    bed.tune_set(torch.float32, ns, {"persistent": 1})
+    A = torch.from_numpy(flat).to(DEV)
+    outs = []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    for rep in range(3):
+        pair = []
+        for st in streams:
+            with torch.cuda.stream(st):
+                lam, Q, info = bed.syevd_packed(ns, A, stream=st)
+            pair.append((lam, Q, info))
+        outs.append(pair)
+    torch.cuda.synchronize()
+    ref_l, ref_q = outs[0][0][0], outs[0][0][1]
+    for pair in outs:
+        for lam, Q, info in pair:
+            assert torch.equal(lam, ref_l) and torch.equal(Q, ref_q)
+            assert int(info.abs().sum()) == 0
+    assert bed.cache_entries() >= 2  # one plan per (size mix, stream)
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    lg, qg = split(ns, ref_l.cpu().numpy(), ref_q.cpu().numpy())
+    lo, qo = split(ns, lam_o, Q_o)
+    worst, fails = compare_batch(mats, lg, qg, lo, qo, np.float32)
+    assert not fails, fails[:3]
+
+
+def test_plan_cache_stays_bounded():
+    """More distinct size mixes than the convenience cache holds: it evicts
+    (after the evicted plans' launches completed) and every result is right."""
+    rng = np.random.default_rng(3300)
+    for i in range(40):
+        ns = [int(v) for v in rng.integers(3, 40, size=5)] + [i + 2]
+        mats = [workloads.gaussian_sym(rng, 1, n)[0].astype(np.float32) for n in ns]
+        _, flat = workloads.pack(mats)
+        lam, Q, info = bed.syevd_packed(ns, torch.from_numpy(flat).to(DEV))
+        assert bed.cache_entries() <= 32
+    torch.cuda.synchronize()
+    lam_o, _, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    assert np.abs(lam.cpu().numpy() - lam_o).max() <= 1e-5 * np.abs(lam_o).max()
