@@ -295,11 +295,72 @@ def backward_leg(bed, torch, steps, warmup):
     wall_f, ev_f = timed(torch, fwd, steps, warmup)
     wall_b, ev_b = timed(torch, bwd, steps, warmup)
     wall_fb, _ = timed(torch, both, steps, warmup)
+    # device time: the calls replayed from HIP graphs (an eager call of the
+    # short backward kernel is paced by the host's launch cost)
+    g_b, g_fb = _graph_of(torch, bwd), _graph_of(torch, both)
+    wall_gb, ev_gb = timed(torch, g_b.replay, steps, warmup)
+    wall_gfb, ev_gfb = timed(torch, g_fb.replay, steps, warmup)
+    ev_gb /= GRAPH_REPS
+    ev_gfb /= GRAPH_REPS
     return {"batch": b, "n": n,
-            "forward_ms": wall_f, "backward_ms": wall_b, "backward_kernel_ms": ev_b,
+            "forward_ms": wall_f, "backward_ms": wall_b, "backward_eager_event_ms": ev_b,
             "forward_backward_ms": wall_fb,
-            "eigendecomps_per_s_fwd_bwd": b / (wall_fb * 1e-3),
-            "backward_tflops": b * backward_flops(n) / (ev_b * 1e-3) / 1e12}
+            "backward_kernel_ms": ev_gb, "forward_backward_graph_ms": ev_gfb,
+            "eigendecomps_per_s_fwd_bwd": b / (ev_gfb * 1e-3),
+            "backward_tflops": b * backward_flops(n) / (ev_gb * 1e-3) / 1e12}
+
+
+GRAPH_REPS = 10
+
+
+def _graph_of(torch, fn, reps=GRAPH_REPS):
+    """reps calls of fn() captured in one HIP graph on a side stream (after one
+    eager warm-up); a replay's time divided by reps is the device time of one
+    call without the launch cost of a graph per call."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(reps):
+            fn()
+    torch.cuda.synchronize()
+    return g
+
+
+def spectral_leg(bed, torch, steps, warmup):
+    """Matrix square root of batch 1024 FP32 covariance matrices n = 32 (the
+    meta-layer use): decomposition + Q sqrt(Lambda) Q^T forward, and the
+    divided-difference backward, replayed from HIP graphs."""
+    from paper_2604_27325_amd import workloads
+    A_np, _, dQ_np, _ = workloads.differentiation()
+    A = torch.from_numpy(A_np).to("cuda")
+    dF = torch.from_numpy(dQ_np).to("cuda")
+    b, n = A.shape[0], A.shape[1]
+    lam, Q = bed.syevd(A)
+    F, dA = torch.empty_like(A), torch.empty_like(A)
+    nl = [n] * b
+
+    def fwd():
+        bed.syevd_packed(nl, A.view(-1), lam=lam.view(-1), Q=Q.view(-1))
+        bed.spectral_apply(lam, Q, "sqrt", out=F)
+
+    def bwd():
+        bed.spectral_backward(lam, Q, dF, "sqrt", out=dA)
+
+    def both():
+        fwd()
+        bwd()
+
+    _, ev_f = timed(torch, _graph_of(torch, fwd).replay, steps, warmup)
+    _, ev_b = timed(torch, _graph_of(torch, bwd).replay, steps, warmup)
+    _, ev_fb = timed(torch, _graph_of(torch, both).replay, steps, warmup)
+    ev_f, ev_b, ev_fb = ev_f / GRAPH_REPS, ev_b / GRAPH_REPS, ev_fb / GRAPH_REPS
+    return {"batch": b, "n": n, "function": "sqrt", "forward_ms": ev_f,
+            "backward_ms": ev_b, "forward_backward_ms": ev_fb,
+            "matrices_per_s_fwd_bwd": b / (ev_fb * 1e-3)}
 
 
 class _ServeData:
@@ -435,6 +496,8 @@ def main():
                     help="only the batch-512 legs (no uneven / backward / serving)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--only-n", type=int, default=0)
+    ap.add_argument("--only-leg", choices=["uneven", "backward", "spectral", "serving"],
+                    default=None, help="run only this leg (for profiler passes); no JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch one 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -449,6 +512,13 @@ def main():
     from paper_2604_27325_amd import workloads
 
     bed.load_library()
+    if args.only_leg:
+        leg = {"uneven": lambda: uneven_leg(bed, torch, args.steps, args.warmup),
+               "backward": lambda: backward_leg(bed, torch, args.steps, args.warmup),
+               "spectral": lambda: spectral_leg(bed, torch, args.steps, args.warmup),
+               "serving": lambda: serving_leg(bed, torch, args.serve_requests)}[args.only_leg]()
+        print(f"[bench] {args.only_leg}: {json.dumps(leg)}", flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(64 << 20, device="cuda")
         dst = torch.empty_like(src)
@@ -480,13 +550,16 @@ def main():
     achieved = BATCH * F / (ev * 1e-3) / 1e12
     import oracle
     parity = parity_sample(oracle, A_np, lam, Q, info)
-    uneven = backward = serving = None
+    uneven = backward = serving = spectral = None
     if not args.no_extra:
         uneven = uneven_leg(bed, torch, max(args.steps // 4, 10), max(args.warmup // 4, 3))
         print(f"[bench] uneven: graph {uneven['graph']['eigendecomps_per_s']:.4g} matrices/s, "
               f"{uneven['speedup_vs_per_size']:.2f}x per-size launches", flush=True)
         backward = backward_leg(bed, torch, args.steps, args.warmup)
         print(f"[bench] backward: {backward['backward_kernel_ms'] * 1e3:.1f} us", flush=True)
+        spectral = spectral_leg(bed, torch, args.steps, args.warmup)
+        print(f"[bench] spectral sqrt: fwd {spectral['forward_ms'] * 1e3:.1f} us, bwd "
+              f"{spectral['backward_ms'] * 1e3:.1f} us", flush=True)
         if not args.no_serve:
             serving = serving_leg(bed, torch, args.serve_requests)
             print(f"[bench] serving: saturation {serving['saturation_matrices_per_s']:.4g} "
@@ -519,6 +592,7 @@ def main():
         "parity": parity,
         "uneven": uneven,
         "backward": backward,
+        "spectral": spectral,
         "serving": serving,
     }
     print(json.dumps(line))

@@ -19,6 +19,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <algorithm>
 #include <thread>
 #include <vector>
 
@@ -40,6 +41,7 @@ struct Request {
     int32_t *info;
     int64_t bytes;
     hipEvent_t ready;  // recorded on the caller's stream at submission
+    hipStream_t producer;
     Clock::time_point t_submit;
     bool launched = false, done = false;
     double latency_us = 0.0;
@@ -130,10 +132,17 @@ static void server_loop(bed_server *s)
                 r.launched = true;
                 sl.tickets.push_back(tk);
             }
-            // every request's input is complete on its producer stream first
+            // every request's input is complete on its producer stream first:
+            // per producer stream, the event of its latest request covers the
+            // earlier ones (work on one stream completes in order)
             hipError_t e = hipSuccess;
-            for (uint64_t tk : sl.tickets)
-                if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream, s->reqs[tk].ready, 0);
+            std::map<hipStream_t, uint64_t> latest;
+            for (uint64_t tk : sl.tickets) {
+                auto &v = latest[s->reqs[tk].producer];
+                v = std::max(v, tk);
+            }
+            for (const auto &kv : latest)
+                if (e == hipSuccess) e = hipStreamWaitEvent(sl.stream, s->reqs[kv.second].ready, 0);
             // stage the list in pinned memory grouped by (dtype, class)
             int off = 0;
             struct Launch {
@@ -262,6 +271,7 @@ extern "C" bed_status bed_server_submit(bed_server *s, bed_dtype dt, int32_t cou
     r.info = info;
     r.bytes = bytes;
     r.ready = ev;
+    r.producer = (hipStream_t)stream;
     r.t_submit = Clock::now();
     s->reqs.emplace(r.ticket, r);
     s->pending.push_back(r.ticket);

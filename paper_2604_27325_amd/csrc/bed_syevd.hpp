@@ -458,7 +458,7 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
             T s0 = 0, s1 = 0, s2 = 0, e = 0;
 #pragma unroll
             for (int j = 0; j < KPL; ++j) {
-                const T rinv = f_rcp_fast(df[j] - hh);
+                const T rinv = f_rcp(df[j] - hh);
                 const T t0 = z2[j] * rinv;
                 const T t1 = t0 * rinv;
                 s0 += t0;
