@@ -390,9 +390,11 @@ class _ServeData:
             oq += c * n * n
 
 
-def _serve_server(bed, data, arrivals, streams=4):
+def _serve_server(bed, data, arrivals, streams=4, producer=None):
     """Open loop through the server (arrivals=None: closed loop, all at t=0).
-    Latency = arrival -> completion observed by the server's scheduler."""
+    Latency = arrival -> completion observed by the server's scheduler.
+    `producer` is the stream the requests name as the producer of their input
+    (None: torch's current stream)."""
     srv = bed.Server(streams=streams)
     R = len(data.req)
     arr = np.zeros(R) if arrivals is None else arrivals
@@ -402,9 +404,9 @@ def _serve_server(bed, data, arrivals, streams=4):
         while time.perf_counter() - t0 < arr[i]:
             pass
         A, lam, Q = data.req[i]
-        tk = srv.submit(A, lam, Q)
+        tk = srv.submit(A, lam, Q, stream=producer)
         while tk is None:
-            tk = srv.submit(A, lam, Q)
+            tk = srv.submit(A, lam, Q, stream=producer)
         sub[i] = time.perf_counter() - t0
         tickets.append(tk)
     srv.drain()
