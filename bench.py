@@ -210,6 +210,32 @@ def cpu_baseline(oracle, A_np, budget_s):
             "context_numpy_eigh_binary64": lapack}
 
 
+def eigenvalues_leg(bed, torch, A, A_np, oracle, steps, warmup):
+    """Eigenvalues only (Sec. 2.3.5: vectors are formed only when required) on
+    the timed workload: per-launch time, rate, and the oracle's eigenvalues on
+    sampled matrices."""
+    b, n = A.shape[0], A.shape[1]
+    lam = torch.empty(b * n, device=A.device, dtype=A.dtype)
+    info = torch.empty(b, dtype=torch.int32, device=A.device)
+    flat, nl = A.view(-1), [n] * b
+    wall, ev, each = timed(torch, lambda: bed.syevd_packed(nl, flat, lam=lam, info=info,
+                                                            want_vectors=False),
+                           steps, warmup, per_step=True)
+    from tests.parity import compare_batch
+    lam = lam.view(b, n).cpu().numpy()
+    idx = np.linspace(0, b - 1, 16).astype(int)
+    lam_o = oracle.syevd(A_np[idx].astype(np.float64))[0]
+    worst, fails = compare_batch(A_np[idx], lam[idx], None, lam_o, None, np.float32,
+                                 info=info.cpu().numpy()[idx])
+    err = float(worst.get("lam", 0.0))
+    return {"eigendecomps_per_s": b / (wall * 1e-3), "ms_per_step": wall, "kernel_ms": ev,
+            "launch_us_median": float(np.median(each) * 1e3),
+            "launch_us_p10": float(np.percentile(each, 10) * 1e3),
+            "launch_us_p90": float(np.percentile(each, 90) * 1e3),
+            "sampled": 16, "failures": len(fails), "max_lambda_err_rel": err,
+            "info_nonzero": int((info.cpu().numpy() != 0).sum())}
+
+
 def uneven_leg(bed, torch, steps, warmup):
     """4096 FP32 matrices, n ~ U{4..64}: autotuned persistent plan replayed from
     a HIP graph, against one plain bed_syevd launch per distinct n."""
@@ -552,6 +578,10 @@ def main():
     achieved = BATCH * F / (ev * 1e-3) / 1e12
     import oracle
     parity = parity_sample(oracle, A_np, lam, Q, info)
+    A = torch.from_numpy(A_np).to("cuda")
+    evals = eigenvalues_leg(bed, torch, A, A_np, oracle, args.steps, args.warmup)
+    print(f"[bench] n={n} eigenvalues only: {evals['eigendecomps_per_s']:.4g} matrices/s, "
+          f"kernel {evals['kernel_ms'] * 1e3:.1f} us", flush=True)
     uneven = backward = serving = spectral = None
     if not args.no_extra:
         uneven = uneven_leg(bed, torch, max(args.steps // 4, 10), max(args.warmup // 4, 3))
@@ -592,6 +622,7 @@ def main():
         "cpu_baseline": cpu,
         "per_n": per_n,
         "parity": parity,
+        "eigenvalues_only": evals,
         "uneven": uneven,
         "backward": backward,
         "spectral": spectral,

@@ -1423,7 +1423,29 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         // K loop has a fixed length (4, 8 or 16 steps, chosen once per row
         // tile) and operands come from clamped addresses, so the tile has no
         // per-step branches.
-        {
+        if (!Q_out) {
+            // Eigenvalues only: the next depth's z (Eq. (5)) reads the last
+            // row of each left child and the first row of each right child,
+            // i.e. the end rows of this depth's nodes -- and an end row of a
+            // node is the matching end row of one child times M.  So only the
+            // two end rows of every node are formed (2 m^2 flops per node
+            // instead of the block product), wave w taking rows w, w + NW, ...
+            // with one lane per column; unmerged leaves pass theirs through M
+            // = I.  The other rows of the buffers are never read again.
+            for (int r = wave; r < n; r += NW) {
+                const int nlo = S.u.m.nlo[r], nhi = S.u.m.nhi[r];
+                if (r != nlo && r != nhi - 1) continue;
+                const int c = lane;
+                if (c < nlo || c >= nhi) continue;
+                const int kl = S.u.m.ckl[r], kh = S.u.m.ckh[r];
+                T acc = T(0);
+                for (int k = kl; k < kh; ++k) acc = fma(Qc[r * LD + k], S.M[k * LD + c], acc);
+                Qn[r * LD + c] = acc;
+            }
+            for (int e = t; e < n; e += NT) {
+                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= LEAF) Ln[e] = Lc[e];
+            }
+        } else {
             constexpr int RT = NMAX / 16;
             constexpr int CG = (NW >= RT) ? NW / RT : 1;    // column groups per row tile
             BED_MARK(d, 0);

@@ -42,7 +42,7 @@ def compare_one(A, lam_g, Q_g, lam_o, Q_o, dtype, check_sign=True):
     A = _sym(A)
     n = A.shape[0]
     lam_g = np.asarray(lam_g, dtype=np.float64)
-    Q_g = np.asarray(Q_g, dtype=np.float64)
+    Q_g = None if Q_g is None else np.asarray(Q_g, dtype=np.float64)
     nrm = max(np.abs(lam_o).max(), 1e-300)
     bad = []
     out = {}

@@ -93,20 +93,38 @@ def test_in_place_and_determinism():
     assert torch.equal(lam3, lam1) and torch.equal(B, Q1)
 
 
-@pytest.mark.parametrize("n", [5, 17, 32, 48, 64])
-def test_eigenvalues_only_matches_oracle(n):
-    """bed_syevals (no eigenvectors) against the oracle's eigenvalues (R1), on
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 9, 16, 17, 31, 32, 33, 48, 63, 64])
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_eigenvalues_only_matches_oracle(n, dt):
+    """bed_syevals (no eigenvectors: only the end rows of every node's block
+    are carried between depths) against the oracle's eigenvalues (R1), on
     Gaussian and covariance matrices and on the planted-pair workload."""
     rng = np.random.default_rng(5 + n)
     A_np = np.concatenate([workloads.gaussian_sym(rng, 16, n), workloads.covariance(rng, 16, n)])
     if n in (32, 48, 64):
         A_np = np.concatenate([A_np, workloads.paper_scale(n)[0][:64]])
-    A_np = A_np.astype(np.float32)
-    lam = bed.syevals(torch.from_numpy(A_np).to(DEV)).cpu().numpy()
+    A_np = A_np.astype(dt)
+    A = torch.from_numpy(A_np).to(DEV)
+    lam, _, info = bed.syevd_packed([n] * A_np.shape[0], A.view(-1), want_vectors=False)
+    lam = lam.view(-1, n).cpu().numpy()
     lam_o, _, _ = oracle.syevd(A_np.astype(np.float64))
-    err = np.abs(lam - lam_o).max(axis=1) / np.abs(lam_o).max(axis=1)
-    print(f"[syevals n={n}] max eigenvalue error {err.max():.3g} x ||A||", flush=True)
-    assert err.max() <= 1e-5
+    worst, fails = compare_batch(A_np, lam, None, lam_o, None, dt, info=info.cpu().numpy())
+    print(f"[syevals n={n} {dt.__name__}] worst {worst}", flush=True)
+    assert not fails, fails[:3]
+
+
+def test_eigenvalues_only_uneven_packed_batch():
+    ns, mats = workloads.uneven(batch=300)
+    _, flat = workloads.pack(mats)
+    lam, _, info = bed.syevd_packed(ns, torch.from_numpy(flat).to(DEV), want_vectors=False)
+    lam, info = lam.cpu().numpy(), info.cpu().numpy()
+    lam_o, _, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    lg = [lam[offs[i]:offs[i + 1]] for i in range(len(ns))]
+    lo = [lam_o[offs[i]:offs[i + 1]] for i in range(len(ns))]
+    worst, fails = compare_batch(mats, lg, None, lo, None, np.float32, info=info)
+    print(f"[syevals uneven] worst {worst}", flush=True)
+    assert not fails, fails[:3]
 
 
 def test_uneven_packed_batch_matches_oracle():

@@ -153,6 +153,14 @@ def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
     worst, fails = compare_batch(mats, lg, qg, lo, qo, npdt, info=info.cpu().numpy())
     print(f"  worst {worst}", flush=True)
     assert not fails, fails[:3]
+    # eigenvalues only (end rows of each node's block carried instead of Q)
+    lam_v = torch.empty_like(lam)
+    plan.run(A, lam_v, None, info)
+    torch.cuda.synchronize()
+    lv, _ = split(ns, lam_v.cpu().numpy(), Q.cpu().numpy())
+    worst_v, fails_v = compare_batch(mats, lv, None, lo, None, npdt, info=info.cpu().numpy())
+    print(f"  eigenvalues only: worst {worst_v}", flush=True)
+    assert not fails_v, fails_v[:3]
 
 
 def test_uneven_workload_full_size_graph_matches_oracle():
