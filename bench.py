@@ -236,6 +236,27 @@ def eigenvalues_leg(bed, torch, A, A_np, oracle, steps, warmup):
             "info_nonzero": int((info.cpu().numpy() != 0).sum())}
 
 
+def leaf_leg(bed, torch, steps, warmup, sizes=(32, 64)):
+    """Per-launch time of the batch-512 solve with leaves of at most 2, 4 or 8
+    elements (Sec. 2.2: the divide step may stop early and hand small blocks to
+    Jacobi); the default cutoff is 4."""
+    from paper_2604_27325_amd import workloads
+    out = {}
+    for n in sizes:
+        A = torch.from_numpy(workloads.paper_scale(n)[0]).to("cuda")
+        flat, nl = A.view(-1), [n] * A.shape[0]
+        lam = torch.empty(A.shape[0] * n, device="cuda")
+        Q = torch.empty_like(flat)
+        row = {}
+        for leaf in (2, 4, 8):
+            plan = bed.Plan(torch.float32, nl, tune={"leaf": leaf})
+            _, ev, each = timed(torch, lambda: plan.run(flat, lam, Q), steps, warmup, per_step=True)
+            row[str(leaf)] = {"kernel_us": ev * 1e3, "launch_us_median": float(np.median(each) * 1e3)}
+            plan.close()
+        out[str(n)] = row
+    return out
+
+
 def uneven_leg(bed, torch, steps, warmup):
     """4096 FP32 matrices, n ~ U{4..64}: autotuned persistent plan replayed from
     a HIP graph, against one plain bed_syevd launch per distinct n."""
@@ -524,7 +545,7 @@ def main():
                     help="only the batch-512 legs (no uneven / backward / serving)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--only-n", type=int, default=0)
-    ap.add_argument("--only-leg", choices=["uneven", "backward", "spectral", "serving"],
+    ap.add_argument("--only-leg", choices=["uneven", "backward", "spectral", "serving", "leaf"],
                     default=None, help="run only this leg (for profiler passes); no JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch one 256 MiB device copy (HBM counter calibration)")
@@ -544,7 +565,8 @@ def main():
         leg = {"uneven": lambda: uneven_leg(bed, torch, args.steps, args.warmup),
                "backward": lambda: backward_leg(bed, torch, args.steps, args.warmup),
                "spectral": lambda: spectral_leg(bed, torch, args.steps, args.warmup),
-               "serving": lambda: serving_leg(bed, torch, args.serve_requests)}[args.only_leg]()
+               "serving": lambda: serving_leg(bed, torch, args.serve_requests),
+               "leaf": lambda: leaf_leg(bed, torch, args.steps, args.warmup)}[args.only_leg]()
         print(f"[bench] {args.only_leg}: {json.dumps(leg)}", flush=True)
         return
     if args.copy_calibration:
@@ -582,8 +604,10 @@ def main():
     evals = eigenvalues_leg(bed, torch, A, A_np, oracle, args.steps, args.warmup)
     print(f"[bench] n={n} eigenvalues only: {evals['eigendecomps_per_s']:.4g} matrices/s, "
           f"kernel {evals['kernel_ms'] * 1e3:.1f} us", flush=True)
-    uneven = backward = serving = spectral = None
+    uneven = backward = serving = spectral = leaves = None
     if not args.no_extra:
+        leaves = leaf_leg(bed, torch, max(args.steps // 2, 10), max(args.warmup // 2, 3))
+        print(f"[bench] leaf cutoff: {json.dumps(leaves)}", flush=True)
         uneven = uneven_leg(bed, torch, max(args.steps // 4, 10), max(args.warmup // 4, 3))
         print(f"[bench] uneven: graph {uneven['graph']['eigendecomps_per_s']:.4g} matrices/s, "
               f"{uneven['speedup_vs_per_size']:.2f}x per-size launches", flush=True)
@@ -623,6 +647,7 @@ def main():
         "per_n": per_n,
         "parity": parity,
         "eigenvalues_only": evals,
+        "leaf_cutoff": leaves,
         "uneven": uneven,
         "backward": backward,
         "spectral": spectral,

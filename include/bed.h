@@ -74,13 +74,17 @@ typedef enum {
  *   order         0: largest n first (LPT), 1: input order
  *   persistent    1: one persistent launch pulls matrices from a device work
  *                 counter (progressive removal at batch level); 0: one
- *                 workgroup per matrix                                          */
+ *                 workgroup per matrix
+ *   leaf          cutoff of the divide step (Sec. 2.2): nodes of at most leaf
+ *                 elements (2, 4 or 8) are solved by cyclic Jacobi instead of
+ *                 being split further; 0: per size class (8 for n > 32, else 4) */
 typedef struct bed_tune {
     int32_t threads_big;
     int32_t threads_mid;
     int32_t waves_per_cu;
     int32_t order;
     int32_t persistent;
+    int32_t leaf;
 } bed_tune;
 
 typedef struct bed_plan bed_plan;

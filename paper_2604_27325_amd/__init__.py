@@ -36,7 +36,7 @@ class BedError(RuntimeError):
 class Tune(ctypes.Structure):
     _fields_ = [("threads_big", ctypes.c_int32), ("threads_mid", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("leaf", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -87,9 +87,11 @@ int size_class(int n) { return n <= 16 ? 0 : (n <= 32 ? 1 : 2); }
 TeamShape class_shape(int cls, const bed_tune &t)
 {
     switch (cls) {
-    case 0: return TeamShape{16, 64};
-    case 1: return TeamShape{32, t.threads_mid > 0 ? t.threads_mid : 128};
-    default: return TeamShape{64, t.threads_big > 0 ? t.threads_big : 512};
+    case 0: return TeamShape{16, 64, t.leaf > 0 ? t.leaf : leaf_default(16)};
+    case 1: return TeamShape{32, t.threads_mid > 0 ? t.threads_mid : 128,
+                             t.leaf > 0 ? t.leaf : leaf_default(32)};
+    default: return TeamShape{64, t.threads_big > 0 ? t.threads_big : 512,
+                              t.leaf > 0 ? t.leaf : leaf_default(64)};
     }
 }
 
@@ -101,6 +103,7 @@ bed_tune default_tune()
     t.waves_per_cu = 0;
     t.order = 0;
     t.persistent = 0;
+    t.leaf = 0;  // per size class
     return t;
 }
 
@@ -199,6 +202,8 @@ extern "C" bed_status bed_plan_create(bed_plan **plan, bed_dtype dt, int64_t bat
     const bed_tune dflt = default_tune();
     if (t.threads_big == 0) t.threads_big = dflt.threads_big;
     if (t.threads_mid == 0) t.threads_mid = dflt.threads_mid;
+    if (t.leaf != 0 && !leaf_supported(t.leaf))
+        return fail(BED_ERR_INVALID_ARG, "unsupported leaf size %d (2, 4 or 8)", t.leaf);
     if (!team_supported(dt, TeamShape{64, t.threads_big}) ||
         !team_supported(dt, TeamShape{32, t.threads_mid}))
         return fail(BED_ERR_INVALID_ARG, "unsupported thread counts (%d, %d)", t.threads_big,

@@ -27,11 +27,18 @@ struct PtrItem {
     int32_t pad;
 };
 
-// Size classes: a team of `nt` threads solves matrices with n <= nmax.
+// Size classes: a team of `nt` threads solves matrices with n <= nmax,
+// splitting the tridiagonal matrix down to leaves of at most `leaf` elements
+// (2, 4 or 8).  Default cutoff per class (measured on the batch-512
+// workloads): 8 for the n > 32 class, whose one fewer merge depth outweighs
+// the longer Jacobi sweeps, 4 below.
+__host__ __device__ constexpr int leaf_default(int nmax) { return nmax >= 64 ? 8 : 4; }
 struct TeamShape {
     int nmax;
     int nt;
+    int leaf = 4;
 };
+inline bool leaf_supported(int leaf) { return leaf == 2 || leaf == 4 || leaf == 8; }
 
 bool team_supported(bed_dtype dt, TeamShape ts);
 

@@ -16,14 +16,14 @@ template <int NMAX, int NT> struct Occ {
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ lam,
-                T *__restrict__ Q, int32_t *__restrict__ info)
+                T *__restrict__ Q, int32_t *__restrict__ info, int leaf)
 {
     __shared__ Smem<T, NMAX, NT> S;
     const int64_t b = blockIdx.x;
     if (b >= batch) return;
     const int64_t n2 = (int64_t)n * n;
     syevd_team<T, NMAX, NT>(A + b * n2, n, lam + b * n, Q ? Q + b * n2 : nullptr,
-                            info ? info + b : nullptr, S, threadIdx.x);
+                            info ? info + b : nullptr, S, threadIdx.x, leaf);
 }
 
 // Static schedule: workgroup b solves item b.  The hardware dispatcher
@@ -32,13 +32,13 @@ k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_list(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
-             int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count)
+             int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count, int leaf)
 {
     __shared__ Smem<T, NMAX, NT> S;
     if ((int)blockIdx.x >= count) return;
     const WorkItem w = items[blockIdx.x];
     syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
-                            info ? info + w.idx : nullptr, S, threadIdx.x);
+                            info ? info + w.idx : nullptr, S, threadIdx.x, leaf);
 }
 
 // Persistent schedule: a fixed grid whose workgroups take matrices from a
@@ -49,7 +49,7 @@ template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_persist(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
                 int32_t *__restrict__ info, const WorkItem *__restrict__ items, int count,
-                int *counter)
+                int *counter, int leaf)
 {
     __shared__ Smem<T, NMAX, NT> S;
     __shared__ int cur;
@@ -65,7 +65,7 @@ k_syevd_persist(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         syevd_team<T, NMAX, NT>(A + w.offA, w.n, lam + w.offL, Q ? Q + w.offA : nullptr,
-                                info ? info + w.idx : nullptr, S, tid);
+                                info ? info + w.idx : nullptr, S, tid, leaf);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -78,12 +78,13 @@ k_syevd_persist(const T *__restrict__ A, T *__restrict__ lam, T *__restrict__ Q,
 
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
-k_syevd_ptrlist(const PtrItem *__restrict__ items, int count)
+k_syevd_ptrlist(const PtrItem *__restrict__ items, int count, int leaf)
 {
     __shared__ Smem<T, NMAX, NT> S;
     if ((int)blockIdx.x >= count) return;
     const PtrItem w = items[blockIdx.x];
-    syevd_team<T, NMAX, NT>((const T *)w.A, w.n, (T *)w.lam, (T *)w.Q, w.info, S, threadIdx.x);
+    syevd_team<T, NMAX, NT>((const T *)w.A, w.n, (T *)w.lam, (T *)w.Q, w.info, S, threadIdx.x,
+                            leaf);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -92,6 +93,7 @@ k_syevd_ptrlist(const PtrItem *__restrict__ items, int count)
 bool team_supported(bed_dtype dt, TeamShape ts)
 {
     (void)dt;
+    if (!leaf_supported(ts.leaf)) return false;
 #define X(NM, NTT) if (ts.nmax == NM && ts.nt == NTT) return true;
     BED_SHAPES(X)
 #undef X
@@ -105,7 +107,7 @@ static hipError_t uniform_t(TeamShape ts, const void *A, int n, int64_t batch, v
 #define X(NM, NTT)                                                                          \
     if (ts.nmax == NM && ts.nt == NTT) {                                                    \
         hipLaunchKernelGGL((k_syevd_uniform<T, NM, NTT>), dim3((unsigned)batch), dim3(NTT), \
-                           0, s, (const T *)A, n, batch, (T *)lam, (T *)Q, info);           \
+                           0, s, (const T *)A, n, batch, (T *)lam, (T *)Q, info, ts.leaf);  \
         return hipGetLastError();                                                           \
     }
     BED_SHAPES(X)
@@ -130,10 +132,11 @@ static hipError_t list_t(TeamShape ts, const void *A, void *lam, void *Q, int32_
         if (counter)                                                                           \
             hipLaunchKernelGGL((k_syevd_persist<T, NM, NTT>), dim3((unsigned)grid), dim3(NTT), \
                                0, s, (const T *)A, (T *)lam, (T *)Q, info, items, count,       \
-                               counter);                                                       \
+                               counter, ts.leaf);                                              \
         else                                                                                   \
             hipLaunchKernelGGL((k_syevd_list<T, NM, NTT>), dim3((unsigned)count), dim3(NTT),   \
-                               0, s, (const T *)A, (T *)lam, (T *)Q, info, items, count);      \
+                               0, s, (const T *)A, (T *)lam, (T *)Q, info, items, count,       \
+                               ts.leaf);                                                       \
         return hipGetLastError();                                                              \
     }
     BED_SHAPES(X)
@@ -156,7 +159,7 @@ static hipError_t ptrlist_t(TeamShape ts, const PtrItem *items, int count, hipSt
 #define X(NM, NTT)                                                                            \
     if (ts.nmax == NM && ts.nt == NTT) {                                                      \
         hipLaunchKernelGGL((k_syevd_ptrlist<T, NM, NTT>), dim3((unsigned)count), dim3(NTT), 0, \
-                           s, items, count);                                                  \
+                           s, items, count, ts.leaf);                                         \
         return hipGetLastError();                                                             \
     }
     BED_SHAPES(X)

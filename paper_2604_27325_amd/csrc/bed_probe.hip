@@ -48,6 +48,7 @@ __device__ long long *g_defl;
         }                                                                                \
     } while (0)
 
+#include "bed_internal.hpp"
 #include "bed_syevd.hpp"
 
 namespace bed {
@@ -62,7 +63,7 @@ k_probe_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
     if (b >= batch) return;
     const int64_t n2 = (int64_t)n * n;
     syevd_team<T, NMAX, NT>(A + b * n2, n, lam + b * n, Q ? Q + b * n2 : nullptr, nullptr, S,
-                            threadIdx.x);
+                            threadIdx.x, leaf_default(NMAX));
 }
 
 #define BED_PROBE_SHAPES(X) X(16, 64) X(32, 64) X(32, 128) X(64, 256) X(64, 512)

@@ -18,6 +18,8 @@
 //   Back-transform: each wave owns NMAX/NW whole columns (no team barrier).
 #pragma once
 
+#include <type_traits>
+
 #include "bed_device.hpp"
 #include "bed_mfma.hpp"
 
@@ -156,9 +158,9 @@ __device__ __forceinline__ int input_shift(const Smem<T, NMAX, NT>& S)
 }
 
 // Node of a dyadic tearing tree over [0, n): node j at depth d covers
-// [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of more than LEAF elements
-// split at the floor of their dyadic midpoint, the others are leaves.
-constexpr int LEAF = 4;
+// [floor(j n / 2^d), floor((j+1) n / 2^d)); nodes of more than `leaf`
+// elements (the cutoff: 2, 4 or 8) split at the floor of their dyadic
+// midpoint, the others are leaves.
 struct Node {
     int lo, hi, s;
 };
@@ -197,19 +199,38 @@ __device__ __forceinline__ void jacobi_rot(const T app, const T aqq, const T apq
     s = rot ? tt * cc : T(0);
 }
 
+// Value of lane ^ K inside aligned groups of 8 lanes: quad-permute DPP for K
+// < 4, a lane shuffle otherwise.
+template <int K, typename T> __device__ __forceinline__ T lxor(T x)
+{
+    if constexpr (K < 4) return qxor<K>(x);
+    else return __shfl_xor(x, K);
+}
+
+// f(integral_constant<int, K>) for K = B, ..., E - 1 (compile-time indices).
+template <int B, int E, typename F> __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 // One simultaneous round of the leaf Jacobi sweep: the pairs (i, i ^ M) of
-// every leaf.  Lane i keeps row i of A and of V = J_1 J_2 ... in XOR-relative
-// order, a[k] = A(i, i ^ k), v[k] = V(i, i ^ k).  With J the product of the
-// round's disjoint rotations, A <- J^T A J and V <- V J: each lane rotates its
-// row's column pairs (j, j ^ M) with the parameters held by lane j, then
-// combines its row with the partner row i ^ M.  The pair's own 2x2 block takes
-// the exact form (a_pq' = 0, a_pp' = a_pp - t a_pq, a_qq' = a_qq + t a_pq).
-template <int M, typename T>
-__device__ __forceinline__ void jacobi_round(T (&a)[4], T (&v)[4], const int i, const int msz)
+// every leaf (GS lanes per leaf).  Lane i keeps row i of A and of V = J_1 J_2
+// ... in XOR-relative order, a[k] = A(i, i ^ k), v[k] = V(i, i ^ k).  With J
+// the product of the round's disjoint rotations, A <- J^T A J and V <- V J:
+// each lane rotates its row's column pairs (j, j ^ M) with the parameters held
+// by lane j, then combines its row with the partner row i ^ M.  The pair's own
+// 2x2 block takes the exact form (a_pq' = 0, a_pp' = a_pp - t a_pq, a_qq' =
+// a_qq + t a_pq).  The rounds M = 1, ..., GS - 1 of a sweep pair every two
+// rows of the leaf exactly once (M = i ^ j).
+template <int GS, int M, typename T>
+__device__ __forceinline__ void jacobi_round(T (&a)[GS], T (&v)[GS], const int i, const int msz)
 {
     const int ip = i ^ M;
-    const T pd = qxor<M>(a[0]);  // A(ip, ip)
-    const T po = qxor<M>(a[M]);  // A(ip, i)
+    const T pd = lxor<M>(a[0]);  // A(ip, ip)
+    const T po = lxor<M>(a[M]);  // A(ip, i)
     const bool low = i < ip;     // this row is p of the pair (p, q), p < q
     // both lanes of the pair form the same a_pq (the rounded rows need not be
     // exactly symmetric)
@@ -223,36 +244,31 @@ __device__ __forceinline__ void jacobi_round(T (&a)[4], T (&v)[4], const int i, 
     const T sg = low ? T(-1) : T(1);  // A'(p, :) = c A(p, :) - s A(q, :), A'(q, :) = c A(q, :) + s A(p, :)
     const T ss = sg * s;
     // column parameters (c_j, sigma_j s_j) of column j = i ^ k
-    T cj[4], sj[4];
+    T cj[GS], sj[GS];
     cj[0] = c;
     sj[0] = ss;
     cj[M] = c;
     sj[M] = -ss;
-    if constexpr (M != 1) {
-        cj[1] = qxor<1>(c);
-        sj[1] = qxor<1>(ss);
-    }
-    if constexpr (M != 2) {
-        cj[2] = qxor<2>(c);
-        sj[2] = qxor<2>(ss);
-    }
-    if constexpr (M != 3) {
-        cj[3] = qxor<3>(c);
-        sj[3] = qxor<3>(ss);
-    }
-    T b[4], w[4];
+    static_for<1, GS>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (k != M) {
+            cj[k] = lxor<k>(c);
+            sj[k] = lxor<k>(ss);
+        }
+    });
+    T b[GS], w[GS];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < GS; ++k) {
         b[k] = fma(sj[k], a[k ^ M], cj[k] * a[k]);
         w[k] = fma(sj[k], v[k ^ M], cj[k] * v[k]);
     }
     // partner row after its column rotation: B(ip, i ^ k) sits in its slot k ^ M
-    T pb[4];
+    T pb[GS];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pb[k] = qxor<M>(b[k ^ M]);
+    for (int k = 0; k < GS; ++k) pb[k] = lxor<M>(b[k ^ M]);
     const T dnew = fma(sg * t, apq, a[0]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < GS; ++k) {
         a[k] = fma(ss, pb[k], c * b[k]);
         v[k] = w[k];
     }
@@ -260,28 +276,29 @@ __device__ __forceinline__ void jacobi_round(T (&a)[4], T (&v)[4], const int i, 
     a[M] = rot ? T(0) : a[M];
 }
 
-// Leaves of at most LEAF elements are solved by cyclic Jacobi (the divide step
-// may stop at small blocks and hand them to another eigensolver, Sec. 2.2).
-// Wave 0: lane (g, i) = (lane / 4, lane % 4) holds row i of the leaf of group
-// g, group g standing for node g of depth D (the first such node of a leaf
-// owns it).  Sweeps of the pairs (i, i ^ m), m = 1, 2, 3, run until every
-// off-diagonal entry is at most 8u ||T_leaf||_F (the wave's largest); the
-// eigenvalues are then ranked ascending and the leaf's block of Q written.
-template <typename T, int NMAX, int NT>
+// Leaves of at most GS elements (the cutoff of the divide step, 2, 4 or 8) are
+// solved by cyclic Jacobi -- the divide step may stop at small blocks and hand
+// them to another eigensolver (Sec. 2.2).  Wave 0: lane (g, i) = (lane / GS,
+// lane % GS) holds row i of the leaf of group g, group g standing for node g
+// of depth D (the first such node of a leaf owns it; 2^D <= 64 / GS for n <=
+// 64).  Sweeps of the rounds M = 1, ..., GS - 1 run until every off-diagonal
+// entry is at most 8u ||T_leaf||_F (the wave's largest); the eigenvalues are
+// then ranked ascending and the leaf's block of Q written.
+template <int GS, typename T, int NMAX, int NT>
 __device__ __forceinline__ void jacobi_leaves(Smem<T, NMAX, NT>& S, const int n, const int D,
                                               const int lane, T* __restrict__ Qc,
                                               T* __restrict__ Lc)
 {
-    static_assert(LEAF == 4 && NMAX <= 64, "at most 16 leaf groups of four lanes");
+    static_assert((GS == 2 || GS == 4 || GS == 8) && NMAX <= 64, "leaf groups of 2, 4 or 8 lanes");
     constexpr int LD = Smem<T, NMAX, NT>::LD;
-    constexpr int CAP = 16;  // sweeps (three suffice in binary32 and binary64 alike)
-    const int g = lane >> 2, i = lane & 3;
+    constexpr int CAP = 16;  // sweeps (three to five suffice in binary32 and binary64 alike)
+    const int g = lane / GS, i = lane % GS;
     const int e0 = (g * n) >> D;  // first element of node g at depth D
     int lo = 0, hi = 0;
     bool found = false;
     for (int d = 0; d <= D; ++d) {
         const Node nd = node_of(e0 < n ? e0 : 0, d, n);
-        const bool hit = !found && nd.hi - nd.lo <= LEAF;
+        const bool hit = !found && nd.hi - nd.lo <= GS;
         lo = hit ? nd.lo : lo;
         hi = hit ? nd.hi : hi;
         found = found || hit;
@@ -289,9 +306,9 @@ __device__ __forceinline__ void jacobi_leaves(Smem<T, NMAX, NT>& S, const int n,
     const bool own = g < (1 << D) && found && lo == e0;
     const int msz = own ? hi - lo : 0;
     const bool row = i < msz;
-    T a[4], v[4];
+    T a[GS], v[GS];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < GS; ++k) {
         const int j = i ^ k;
         const bool ok = row && j < msz;
         const bool adj = j == i + 1 || j == i - 1;
@@ -304,34 +321,31 @@ __device__ __forceinline__ void jacobi_leaves(Smem<T, NMAX, NT>& S, const int n,
     }
     T f2 = T(0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) f2 = fma(a[k], a[k], f2);
-    f2 = group_sum<4>(f2, lane);
+    for (int k = 0; k < GS; ++k) f2 = fma(a[k], a[k], f2);
+    f2 = group_sum<GS>(f2, lane);
     const T thr = T(8) * fp<T>::u * f_sqrt(f2);
     for (int sw = 0; sw < CAP; ++sw) {
-        const T off = f_max(f_abs(a[1]), f_max(f_abs(a[2]), f_abs(a[3])));
+        T off = T(0);
+#pragma unroll
+        for (int k = 1; k < GS; ++k) off = f_max(off, f_abs(a[k]));
         if (!__ballot(off > thr)) break;
-        jacobi_round<1>(a, v, i, msz);
-        jacobi_round<2>(a, v, i, msz);
-        jacobi_round<3>(a, v, i, msz);
+        static_for<1, GS>([&](auto K) { jacobi_round<GS, decltype(K)::value>(a, v, i, msz); });
     }
     // ascending rank of this row's eigenvalue among the leaf's (ties by index)
     int rk = 0;
-    {
-        const T o1 = qxor<1>(a[0]), o2 = qxor<2>(a[0]), o3 = qxor<3>(a[0]);
-        rk += ((i ^ 1) < msz && (o1 < a[0] || (o1 == a[0] && (i ^ 1) < i))) ? 1 : 0;
-        rk += ((i ^ 2) < msz && (o2 < a[0] || (o2 == a[0] && (i ^ 2) < i))) ? 1 : 0;
-        rk += ((i ^ 3) < msz && (o3 < a[0] || (o3 == a[0] && (i ^ 3) < i))) ? 1 : 0;
-    }
-    int rj[4];
+    static_for<1, GS>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        const T o = lxor<k>(a[0]);
+        rk += ((i ^ k) < msz && (o < a[0] || (o == a[0] && (i ^ k) < i))) ? 1 : 0;
+    });
+    int rj[GS];
     rj[0] = rk;
-    rj[1] = qxor<1>(rk);
-    rj[2] = qxor<2>(rk);
-    rj[3] = qxor<3>(rk);
+    static_for<1, GS>([&](auto K) { rj[decltype(K)::value] = lxor<decltype(K)::value>(rk); });
     if (row) {
         Lc[lo + rk] = a[0];
         // V(i, j) is entry i of the eigenvector of eigenvalue j
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < GS; ++k)
             if ((i ^ k) < msz) Qc[(lo + i) * LD + lo + rj[k]] = v[k];
     }
 }
@@ -398,7 +412,7 @@ __device__ __forceinline__ T pick(const T* a, int idx)
 // so fewer lanes per root cost less issue time than they add in sums.
 template <typename T, int NMAX, int NT, int SL, int KPL>
 __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n, const int d,
-                                              const int t)
+                                              const int t, const int leaf)
 {
     constexpr int LPR = SL;
     const int lane = t & 63;
@@ -408,7 +422,7 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
     const T FAR = sizeof(T) == 4 ? T(1e30f) : T(1e300);
     const int q = t / LPR, sub = t % LPR;
     const Node qn = node_of(q < n ? q : 0, d, n);
-    const bool qact = (q < n) && (qn.hi - qn.lo > LEAF);
+    const bool qact = (q < n) && (qn.hi - qn.lo > leaf);
     const int qlo = qn.lo;
     const int kq = qact ? S.u.m.nk[qlo] : 0;
     const int jr = q - qlo;
@@ -581,7 +595,7 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
 // merge-matrix assembly (incl. type-2 rotations).  All team threads call it.
 template <typename T, int NMAX, int NT, int KPL>
 __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n, const int d,
-                                              const int t0, T* __restrict__ Ln)
+                                              const int t0, T* __restrict__ Ln, const int leaf)
 {
     constexpr int LD = Smem<T, NMAX, NT>::LD;
     constexpr int LPR = NT / NMAX;
@@ -594,7 +608,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     (void)lane;
     const int q = t / LPR, sub = t % LPR;
     const Node qn = node_of(q < n ? q : 0, d, n);
-    const bool qact = (q < n) && (qn.hi - qn.lo > LEAF);
+    const bool qact = (q < n) && (qn.hi - qn.lo > leaf);
     const int qlo = qn.lo;
     const int mq = qn.hi - qn.lo;
     const int kq = qact ? S.u.m.nk[qlo] : 0;
@@ -606,7 +620,7 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
     // ---- M2: secular roots --------------------------------------------------
     {
         constexpr int SL = LPR < 4 ? LPR : 4;
-        if (t < NMAX * SL) secular_roots<T, NMAX, NT, SL, KPL * LPR / SL>(S, n, d, t);
+        if (t < NMAX * SL) secular_roots<T, NMAX, NT, SL, KPL * LPR / SL>(S, n, d, t, leaf);
     }
     team_sync<NT>();
     BED_PHASE(10 + 8 * d + 1);
@@ -707,15 +721,16 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
 // Calls roots_vectors with the smallest power-of-two KPL >= need.
 template <typename T, int NMAX, int NT, int KPL>
 __device__ __forceinline__ void roots_vectors_dispatch(Smem<T, NMAX, NT>& S, const int n,
-                                                       const int d, const int t, T* Ln, int need)
+                                                       const int d, const int t, T* Ln, int need,
+                                                       const int leaf)
 {
     if constexpr (KPL >= NMAX / (NT / NMAX)) {
-        roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln);
+        roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln, leaf);
     } else {
         if (need <= KPL)
-            roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln);
+            roots_vectors<T, NMAX, NT, KPL>(S, n, d, t, Ln, leaf);
         else
-            roots_vectors_dispatch<T, NMAX, NT, KPL * 2>(S, n, d, t, Ln, need);
+            roots_vectors_dispatch<T, NMAX, NT, KPL * 2>(S, n, d, t, Ln, need, leaf);
     }
 }
 
@@ -1071,7 +1086,7 @@ template <typename T, int NMAX, int NT>
 __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int n,
                                            T* __restrict__ lam_out, T* __restrict__ Q_out,
                                            int* __restrict__ info_out, Smem<T, NMAX, NT>& S,
-                                           const int t)
+                                           const int t, const int leaf = 4)
 {
     static_assert(NMAX <= 64 && (NMAX & (NMAX - 1)) == 0, "NMAX: power of two <= 64");
     static_assert(NT % 64 == 0 && NT >= NMAX && NT % NMAX == 0, "team geometry");
@@ -1185,7 +1200,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
 
     // ------------------------------------------------------------ tear + leaves
     int D = 0;  // depth of the smallest leaves
-    while (((n + (1 << D) - 1) >> D) > LEAF) ++D;
+    while (((n + (1 << D) - 1) >> D) > leaf) ++D;
     T* Qc = S.Q0;
     T* Qn = S.Q1;
     T* Lc = S.lam0;
@@ -1193,18 +1208,20 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     if (wave == 0) {
         const int e = lane;
         T ae = (e < n) ? S.a[e] : T(0);
-        // Eq. (3): every split s of a node with more than LEAF elements
+        // Eq. (3): every split s of a node with more than `leaf` elements
         // subtracts |b_{s-1}| from a_{s-1} and a_s (branch-free: every depth's
         // coupling is read from a clamped address and applied by a select)
         for (int d = 0; d < D; ++d) {
             const Node nd = node_of(e < n ? e : 0, d, n);
-            const bool split = nd.hi - nd.lo > LEAF && (e == nd.s - 1 || e == nd.s);
+            const bool split = nd.hi - nd.lo > leaf && (e == nd.s - 1 || e == nd.s);
             const T bs = S.b[nd.s >= 1 ? nd.s - 1 : 0];
             ae -= (e < n && split) ? f_abs(bs) : T(0);
         }
         if (e < n) S.a[e] = ae;  // torn diagonal
         wave_sync();
-        jacobi_leaves<T, NMAX, NT>(S, n, D, lane, Qc, Lc);
+        if (leaf <= 2) jacobi_leaves<2>(S, n, D, lane, Qc, Lc);
+        else if (leaf <= 4) jacobi_leaves<4>(S, n, D, lane, Qc, Lc);
+        else jacobi_leaves<8>(S, n, D, lane, Qc, Lc);
     }
     team_sync<NT>();
     BED_PHASE(3);
@@ -1216,7 +1233,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         if (wave == NW - 1) {
             const int e = lane;
             const Node nd = node_of(e < n ? e : 0, d, n);
-            const bool act = (e < n) && (nd.hi - nd.lo > LEAF);
+            const bool act = (e < n) && (nd.hi - nd.lo > leaf);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
             {
                 // Rows of a leaf that is not merged at this depth pass through
@@ -1248,7 +1265,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const int e = lane;
             const Node nd = node_of(e < n ? e : 0, d, n);
             BED_MARK(d, 8);
-            const bool act = (e < n) && (nd.hi - nd.lo > LEAF);
+            const bool act = (e < n) && (nd.hi - nd.lo > leaf);
             const int lo = act ? nd.lo : e, hi = act ? nd.hi : e, s = nd.s;
             const T bet = act ? S.b[s - 1] : T(0);
             const T rho = f_abs(bet);
@@ -1409,7 +1426,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         {
             // poles (and items) per lane at this depth: ceil(max node size / LPR)
             const int need = ((((n + (1 << d) - 1) >> d)) + LPR - 1) / LPR;
-            roots_vectors_dispatch<T, NMAX, NT, 1>(S, n, d, t, Ln, need);
+            roots_vectors_dispatch<T, NMAX, NT, 1>(S, n, d, t, Ln, need, leaf);
         }
         BED_PHASE(10 + 8 * d + 4);
 
@@ -1443,7 +1460,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 Qn[r * LD + c] = acc;
             }
             for (int e = t; e < n; e += NT) {
-                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= LEAF) Ln[e] = Lc[e];
+                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= leaf) Ln[e] = Lc[e];
             }
         } else {
             constexpr int RT = NMAX / 16;
@@ -1471,7 +1488,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             BED_MARK(d, 2);
             // eigenvalues of nodes not merged at this depth
             for (int e = t; e < n; e += NT) {
-                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= LEAF) Ln[e] = Lc[e];
+                if (S.u.m.nhi[e] - S.u.m.nlo[e] <= leaf) Ln[e] = Lc[e];
             }
             BED_MARK(d, 3);
         }

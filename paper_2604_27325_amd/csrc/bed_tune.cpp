@@ -1,8 +1,9 @@
 // bed_tune.cpp -- autotuner for plan schedules.
 //
 // A schedule (bed_tune) picks, per size mix: the team size of the n > 32 and
-// 16 < n <= 32 classes, persistent vs. one-workgroup-per-matrix launches and
-// the list order.  Candidates are timed with HIP events on the caller's
+// 16 < n <= 32 classes, persistent vs. one-workgroup-per-matrix launches, the
+// list order and the leaf cutoff of the divide step (Sec. 2.2: leaves of at
+// most 2, 4 or 8 elements, solved by Jacobi).  Candidates are timed with HIP events on the caller's
 // stream; the winner is cached per (device arch, dtype, histogram of n) in
 // the process and, when BED_TUNE_CACHE names a file, in that JSON file.
 #include <algorithm>
@@ -64,10 +65,11 @@ void load_file_locked()
     char line[512];
     while (fgets(line, sizeof line, f)) {
         char key[256];
-        bed_tune t;
-        if (sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d , %d , %d ]", key, &t.threads_big,
-                   &t.threads_mid, &t.waves_per_cu, &t.order, &t.persistent) == 6)
-            g_tuned[key] = t;
+        bed_tune t = default_tune();
+        const int got = sscanf(line, " \"%255[^\"]\" : [ %d , %d , %d , %d , %d , %d ]", key,
+                               &t.threads_big, &t.threads_mid, &t.waves_per_cu, &t.order,
+                               &t.persistent, &t.leaf);
+        if (got >= 6 && (t.leaf == 0 || leaf_supported(t.leaf))) g_tuned[key] = t;
     }
     fclose(f);
 }
@@ -82,8 +84,8 @@ void save_file_locked()
     size_t i = 0;
     for (const auto &kv : g_tuned) {
         const bed_tune &t = kv.second;
-        fprintf(f, "  \"%s\" : [ %d , %d , %d , %d , %d ]%s\n", kv.first.c_str(), t.threads_big,
-                t.threads_mid, t.waves_per_cu, t.order, t.persistent,
+        fprintf(f, "  \"%s\" : [ %d , %d , %d , %d , %d , %d ]%s\n", kv.first.c_str(),
+                t.threads_big, t.threads_mid, t.waves_per_cu, t.order, t.persistent, t.leaf,
                 ++i < g_tuned.size() ? "," : "");
     }
     fprintf(f, "}\n");
@@ -123,6 +125,7 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
                 t.waves_per_cu = 0;
                 t.order = 0;
                 t.persistent = pers;
+                t.leaf = 0;
                 cands.push_back(t);
             }
     hipEvent_t e0, e1;
@@ -130,9 +133,9 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
         return fail(BED_ERR_HIP, "hipEventCreate failed");
     float best_ms = 1e30f;
     bed_tune best = default_tune();
-    for (const bed_tune &t : cands) {
+    auto trial = [&](const bed_tune &t) {
         bed_plan *p = nullptr;
-        if (bed_plan_create(&p, dt, batch, n, &t, stream) != BED_OK) continue;
+        if (bed_plan_create(&p, dt, batch, n, &t, stream) != BED_OK) return;
         bool ok = true;
         for (int w = 0; w < 2 && ok; ++w) ok = plan_run_impl(p, A, lambda, Q, nullptr, s) == BED_OK;
         const int reps = 5;
@@ -149,6 +152,14 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
         }
         (void)hipStreamSynchronize(s);
         bed_plan_destroy(p);
+    };
+    for (const bed_tune &t : cands) trial(t);
+    // then the leaf cutoff, with the best team shapes and launch form
+    const bed_tune shape = best;
+    for (int leaf : {2, 4, 8}) {
+        bed_tune t = shape;
+        t.leaf = leaf;
+        trial(t);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -172,6 +183,8 @@ extern "C" bed_status bed_tune_set(bed_dtype dt, int64_t batch, const int32_t *n
     const bed_tune dflt = default_tune();
     if (t.threads_big == 0) t.threads_big = dflt.threads_big;
     if (t.threads_mid == 0) t.threads_mid = dflt.threads_mid;
+    if (t.leaf != 0 && !leaf_supported(t.leaf))
+        return fail(BED_ERR_INVALID_ARG, "unsupported leaf size %d (2, 4 or 8)", t.leaf);
     if (!team_supported(dt, TeamShape{64, t.threads_big}) ||
         !team_supported(dt, TeamShape{32, t.threads_mid}))
         return fail(BED_ERR_INVALID_ARG, "unsupported thread counts (%d, %d)", t.threads_big,

@@ -22,9 +22,11 @@ SUB_NAMES = {1: "dot product", 2: "partial exchange + barrier", 3: "reduction p^
 
 
 def phase_names(n):
-    """(id, name) in execution order for order n (leaves of at most 4)."""
+    """(id, name) in execution order for order n (leaves of at most 8 elements
+    for n > 32, else 4: the library's default cutoffs)."""
+    leaf = 8 if n > 32 else 4
     D = 0
-    while ((n + (1 << D) - 1) >> D) > 4:
+    while ((n + (1 << D) - 1) >> D) > leaf:
         D += 1
     out = [(1, "load"), (2, "Householder (+ Q_H)"), (3, "tear + leaves")]
     for d in range(D - 1, -1, -1):

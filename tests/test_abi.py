@@ -96,3 +96,16 @@ def test_probe_library_exports_its_header():
     out = subprocess.run(["nm", "-D", "--defined-only", probe_so], capture_output=True, text=True,
                          check=True).stdout
     assert "bed_probe_phases" in set(re.findall(r"\sT\s(bed_\w+)", out))
+
+
+def test_tune_rejects_unsupported_leaf_size(lib):
+    """The leaf cutoff of the divide step is 2, 4 or 8, or 0 for the per-class
+    default (checked before any HIP call)."""
+    from paper_2604_27325_amd import Tune
+    lib.bed_last_error.restype = ctypes.c_char_p
+    i32 = ctypes.c_int32
+    n = (i32 * 2)(8, 40)
+    for leaf in (1, 3, 5, 16, -2):
+        t = Tune(threads_big=512, threads_mid=128, leaf=leaf)
+        assert lib.bed_tune_set(0, 2, n, ctypes.byref(t)) == 1  # BED_ERR_INVALID_ARG
+        assert b"leaf" in lib.bed_last_error()

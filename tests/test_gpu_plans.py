@@ -106,6 +106,7 @@ def test_autotune_returns_valid_schedule(uneven):
     Q = torch.empty_like(A)
     t = bed.autotune(torch.float32, ns, A, lam, Q)
     assert t["threads_big"] in (128, 256, 512) and t["threads_mid"] in (64, 128)
+    assert t["leaf"] in (0, 2, 4, 8)
     plan = bed.Plan(torch.float32, ns, tune=t)
     l2, q2, info = run_plan(plan, ns, A)
     lam_o, _, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
@@ -160,6 +161,46 @@ def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
     lv, _ = split(ns, lam_v.cpu().numpy(), Q.cpu().numpy())
     worst_v, fails_v = compare_batch(mats, lv, None, lo, None, npdt, info=info.cpu().numpy())
     print(f"  eigenvalues only: worst {worst_v}", flush=True)
+    assert not fails_v, fails_v[:3]
+
+
+@pytest.mark.parametrize("leaf", [2, 4, 8])
+@pytest.mark.parametrize("big,mid", [(512, 128), (128, 64)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_leaf_cutoff_variants_match_oracle(dtype, big, mid, leaf):
+    """Leaves of at most 2, 4 or 8 elements (Sec. 2.2), at every n from 1 to
+    64 and on the planted-pair workload (close pairs that deflate), with and
+    without eigenvectors."""
+    rng = np.random.default_rng(3300 + leaf)
+    ns = list(range(1, 65))
+    mats = [workloads.gaussian_sym(rng, 1, n)[0] for n in ns]
+    for n in (32, 48, 64):
+        planted = workloads.paper_scale(n)[0][:8]
+        mats += list(planted)
+        ns += [n] * len(planted)
+    _, flat = workloads.pack(mats)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    flat = flat.astype(npdt)
+    plan = bed.Plan(dtype, ns, tune={"threads_big": big, "threads_mid": mid, "leaf": leaf})
+    assert plan.tune()["leaf"] == leaf
+    print(f"[leaf={leaf} dtype={dtype} big={big} mid={mid}]", flush=True)
+    A = torch.from_numpy(flat).to(DEV)
+    lam = torch.empty(int(np.sum(ns)), dtype=dtype, device=DEV)
+    Q = torch.empty_like(A)
+    info = torch.empty(len(ns), dtype=torch.int32, device=DEV)
+    plan.run(A, lam, Q, info)
+    torch.cuda.synchronize()
+    lam_o, Q_o, _ = oracle.syevd_packed(ns, flat.astype(np.float64))
+    lg, qg = split(ns, lam.cpu().numpy(), Q.cpu().numpy())
+    lo, qo = split(ns, lam_o, Q_o)
+    worst, fails = compare_batch(mats, lg, qg, lo, qo, npdt, info=info.cpu().numpy())
+    print(f"  worst {worst}", flush=True)
+    assert not fails, fails[:3]
+    lam_v = torch.empty_like(lam)
+    plan.run(A, lam_v, None, info)
+    torch.cuda.synchronize()
+    lv, _ = split(ns, lam_v.cpu().numpy(), Q.cpu().numpy())
+    worst_v, fails_v = compare_batch(mats, lv, None, lo, None, npdt, info=info.cpu().numpy())
     assert not fails_v, fails_v[:3]
 
 
