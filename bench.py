@@ -545,6 +545,7 @@ def main():
                     help="only the batch-512 legs (no uneven / backward / serving)")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--only-n", type=int, default=0)
+    ap.add_argument("--no-big", action="store_true", help="skip the n = 128 entry of per_n")
     ap.add_argument("--only-leg", choices=["uneven", "backward", "spectral", "serving", "leaf"],
                     default=None, help="run only this leg (for profiler passes); no JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -594,6 +595,29 @@ def main():
               f"kernel {ev * 1e3:.1f} us", flush=True)
         if n == sizes[-1]:
             main_res = (n, A_np, wall, ev, lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy())
+
+    if not args.only_n and not args.no_big:
+        # 64 < n <= 128: one more tearing step above the n <= 64 kernels
+        nb = 128
+        A_np_b, _, _ = workloads.paper_scale(nb)
+        A_b = torch.from_numpy(A_np_b).to("cuda")
+        wall_b, ev_b, each_b, lam_b, Q_b, info_b = time_solver(bed, torch, A_b,
+                                                              max(args.steps // 4, 10),
+                                                              max(args.warmup // 4, 3))
+        import oracle as _orc
+        F_b = flop_model(nb)
+        per_n[str(nb)] = {"eigendecomps_per_s": BATCH / (wall_b * 1e-3), "ms_per_step": wall_b,
+                          "kernel_ms": ev_b, "tflops_model": BATCH * F_b / (ev_b * 1e-3) / 1e12,
+                          "flops_per_matrix": F_b,
+                          "launch_us_median": float(np.median(each_b) * 1e3),
+                          "launch_us_p10": float(np.percentile(each_b, 10) * 1e3),
+                          "launch_us_p90": float(np.percentile(each_b, 90) * 1e3),
+                          "kernels": "reduce + tear, halves on the n <= 64 kernels, top merge",
+                          "parity": parity_sample(_orc, A_np_b, lam_b.cpu().numpy(),
+                                                  Q_b.cpu().numpy(), info_b.cpu().numpy())}
+        print(f"[bench] n={nb}: {per_n[str(nb)]['eigendecomps_per_s']:.4g} matrices/s, "
+              f"{ev_b * 1e3:.1f} us per solve", flush=True)
+        del A_b, lam_b, Q_b
 
     n, A_np, wall, ev, lam, Q, info = main_res
     F = flop_model(n)

@@ -4,7 +4,8 @@
  * Method: Householder tridiagonalization followed by the batch-efficient
  * divide-and-conquer of Y. Song, "A Short Note on Batch-efficient Divide-and-
  * Conquer Algorithm for EigenDecomposition" (arXiv 2604.27325): rank-one
- * tearing (Sec. 2.1, Eq. (1)-(3)), 2x2 Givens leaves (Sec. 2.2), secular
+ * tearing (Sec. 2.1, Eq. (1)-(3)), leaves of at most 2, 4 or 8 elements solved
+ * by cyclic Jacobi (Sec. 2.2; the cutoff is a schedule choice), secular
  * equation under bounded interlacing (Sec. 2.3.1, Eq. (8)-(12)), hybrid-section
  * (Sec. 2.3.2, Eq. (13)-(17)), Halley (Sec. 2.3.3, Eq. (20)-(21)), progressive
  * removal of converged work (Sec. 2.3.4, Eq. (22)) and Loewner/Gu-Eisenstat
@@ -22,7 +23,10 @@
  *   Output     lambda ascending; Q[b][i][j] = component i of eigenvector j;
  *              each column sign-canonical (largest-magnitude entry positive,
  *              lowest index on exact ties).
- *   Sizes      1 <= n_b <= 64.  n_b > 64 is reserved (BED_ERR_UNSUPPORTED).
+ *   Sizes      1 <= n_b <= 64 everywhere.  bed_syevd and bed_syevals also
+ *              take uniform binary32 batches of 64 < n <= 128 (one more
+ *              tearing step above the n <= 64 kernels, Sec. 2.1); other uses
+ *              of n > 64 return BED_ERR_UNSUPPORTED.
  *   Memory     A, lambda, Q, info, dlambda, dQ, dA are DEVICE pointers owned
  *              by the caller.  n arrays are HOST pointers, read during the
  *              call only.  FP32 data needs 4-byte, FP64 8-byte alignment.
@@ -57,7 +61,7 @@ typedef enum { BED_F32 = 0, BED_F64 = 1 } bed_dtype;
 typedef enum {
     BED_OK = 0,
     BED_ERR_INVALID_ARG = 1, /* bad size, null or misaligned pointer, bad dtype   */
-    BED_ERR_UNSUPPORTED = 2, /* n > 64                                            */
+    BED_ERR_UNSUPPORTED = 2, /* n > 64 where not supported (see Sizes), n > 128   */
     BED_ERR_HIP = 3,         /* a HIP runtime call failed (see bed_last_error)    */
     BED_ERR_NOMEM = 4,       /* device or host allocation failed / over budget    */
     BED_ERR_CAPTURE = 5,     /* call would allocate or copy during stream capture */
@@ -93,7 +97,11 @@ typedef struct bed_plan bed_plan;
  * no-op.  A uniform batch is one launch with no descriptor.  Mixed sizes (or
  * a stored persistent schedule) use a plan from an internal cache keyed by
  * (dtype, n[], stream); the first call for a new key allocates its descriptor
- * (refused under capture, BED_ERR_CAPTURE). */
+ * (refused under capture, BED_ERR_CAPTURE).  A uniform binary32 batch of
+ * 64 < n <= 128 runs three steps (reduction and tearing, the two halves on
+ * the n <= 64 kernels, the top merge) with a workspace kept per stream
+ * (about 16 (n/2)^2 + 4n + 16 bytes per matrix, grown on demand; growing it
+ * synchronizes the stream and is refused under capture). */
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);
 
@@ -116,8 +124,10 @@ bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *
 bed_status bed_syevd_noalloc(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
                              void *lambda, void *Q, int32_t *info, void *stream);
 
-/* Eigenvalues only (the note computes eigenvectors "when required",
- * Sec. 2.3.5): Q is not produced; same kernel path, no Q store. */
+/* Eigenvalues only (the note forms eigenvectors only when they are required,
+ * Sec. 2.3.5): Q is not produced.  The merges carry only the first and last
+ * row of each node's eigenvector block -- all that the next z (Eq. (5))
+ * reads -- instead of the block product, and there is no back-transform. */
 bed_status bed_syevals(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
                        void *lambda, int32_t *info, void *stream);
 

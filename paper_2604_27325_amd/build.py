@@ -21,7 +21,7 @@ ARCH = os.environ.get("BED_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["bed_kernels.hip", "bed_backward.hip", "bed_api.cpp", "bed_backward_api.cpp",
-           "bed_tune.cpp", "bed_server.cpp", "bed_noalloc.hip", "bed_spectral.hip"]
+           "bed_tune.cpp", "bed_server.cpp", "bed_noalloc.hip", "bed_spectral.hip", "bed_big.hip"]
 PROBE_SOURCES = ["bed_probe.hip"]
 
 # Every HIP translation unit is compiled with packed-FP32 instruction

@@ -41,7 +41,7 @@ bed_status hip_fail(hipError_t e, const char *what)
 
 size_t dtype_size(bed_dtype dt) { return dt == BED_F64 ? 8 : 4; }
 
-bed_status check_sizes(bed_dtype dt, int64_t batch, const int32_t *n)
+bed_status check_sizes(bed_dtype dt, int64_t batch, const int32_t *n, int nmax)
 {
     if (dt != BED_F32 && dt != BED_F64) return fail(BED_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
     if (batch < 0) return fail(BED_ERR_INVALID_ARG, "batch < 0");
@@ -49,8 +49,9 @@ bed_status check_sizes(bed_dtype dt, int64_t batch, const int32_t *n)
     if (batch > (int64_t)INT32_MAX) return fail(BED_ERR_INVALID_ARG, "batch too large");
     for (int64_t b = 0; b < batch; ++b) {
         if (n[b] < 1) return fail(BED_ERR_INVALID_ARG, "n[%lld] = %d < 1", (long long)b, n[b]);
-        if (n[b] > 64)
-            return fail(BED_ERR_UNSUPPORTED, "n[%lld] = %d > 64 is not supported", (long long)b, n[b]);
+        if (n[b] > nmax)
+            return fail(BED_ERR_UNSUPPORTED, "n[%lld] = %d > %d is not supported here",
+                        (long long)b, n[b], nmax);
     }
     return BED_OK;
 }
@@ -307,14 +308,20 @@ void release_cached(CachedPlan &c)
 static bed_status solve(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                         void *Q, int32_t *info, void *stream, bool want_q)
 {
-    bed_status st = check_sizes(dt, batch, n);
+    bed_status st = check_sizes(dt, batch, n, NMAX_BIG);
     if (st != BED_OK) return st;
     if (batch == 0) return BED_OK;
+    const bool uniform = std::all_of(n, n + batch, [&](int32_t v) { return v == n[0]; });
+    const bool big = std::any_of(n, n + batch, [](int32_t v) { return v > 64; });
+    if (big && !uniform)
+        return fail(BED_ERR_UNSUPPORTED, "n > 64 is supported in uniform batches only");
+    if (big && dt != BED_F32)
+        return fail(BED_ERR_UNSUPPORTED, "n = %d > 64 is supported in binary32 only", n[0]);
     if ((st = check_ptr(A, dt, "A", false)) != BED_OK) return st;
     if ((st = check_ptr(lambda, dt, "lambda", false)) != BED_OK) return st;
     if (want_q && (st = check_ptr(Q, dt, "Q", false)) != BED_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const bool uniform = std::all_of(n, n + batch, [&](int32_t v) { return v == n[0]; });
+    if (big) return big_solve(dt, batch, n[0], A, lambda, want_q ? Q : nullptr, info, s);
     if (uniform) {
         // no descriptor needed: one workgroup per matrix, offsets in-kernel
         bed_tune t = tuned_or_default(dt, batch, n);

@@ -1,0 +1,631 @@
+// bed_big.hip -- symmetric matrices of order 64 < n <= 128 in binary32.  The
+// divide step of the note applies at any size (Sec. 2.1): one tearing step
+// above the n <= 64 solver, whose halves then fit a single team, and the top
+// merge (Sec. 2.3) on one 512-thread team per matrix, with the merge code of
+// the n <= 64 solver laid out for 128 elements.
+//
+//   k_big_reduce  Householder tridiagonalization T = Q_H^T A Q_H with binary64
+//                 arithmetic (as for n <= 64); Q_H = H_0 ... H_{n-3} formed
+//                 explicitly and staged in the Q output; T torn at s =
+//                 floor(n/2) (Eq. (3)) into T1 (s x s) and T2 ((n-s) x (n-s)),
+//                 written as dense tridiagonal matrices
+//   children      the n <= 64 kernels solve T1 and T2 (their Householder
+//                 steps are identities: a sub-column that is zero past its
+//                 first entry gives tau = 0)
+//   k_big_merge   z = [sgn(beta) Q1(s-1, :), Q2(0, :)] (Eq. (5)), deflation,
+//                 secular roots, Loewner vectors and the merge matrix M;
+//                 Q = (Q_H diag(Q1, Q2)) M on 16x16x4 MFMA tiles, sign rule
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "bed_host.hpp"
+#include "bed_internal.hpp"
+#include "bed_lru.hpp"
+#include "bed_syevd.hpp"
+
+namespace bed {
+namespace big {
+
+constexpr int BN = NMAX_BIG;  // largest order
+constexpr int BT = 512;       // threads per matrix (8 waves)
+constexpr int CPL = BN * BN / BT;  // matrix entries per lane (32)
+
+struct Meta {
+    float beta;  // coupling b_{s-1} of the torn tridiagonal matrix (scaled)
+    int shift;   // the matrix was solved as 2^shift A
+    int bad;     // non-finite input
+    int pad;
+};
+
+// Workspace of one batch: children (dense input, eigenvectors, eigenvalues,
+// info) and per-matrix meta data.  For even n the two children's arrays are
+// contiguous (child 2 of matrix b follows all children 1), so one uniform
+// launch solves both.
+struct Ws {
+    float *c1, *c2;  // dense tridiagonal children, batch x n1^2 and batch x n2^2
+    float *q1, *q2;  // their eigenvectors
+    float *l1, *l2;  // their eigenvalues
+    int32_t *i1, *i2;
+    Meta *meta;
+};
+
+// ------------------------------------------------------------------ reduction
+struct RedSmem {
+    double V[BN * BN];     // reflector v_k in row k (zero at rows <= k)
+    double x[BN];          // pivot column of the step
+    double w[BN];          // w = p - (tau/2)(p^T v) v
+    double part[2][4][BN]; // per column group: partial products
+    double red[8];         // per wave: partial sums
+    double red2[8];
+    double tau[BN];
+    float a[BN], b[BN];
+    int badw[BT / 64];
+    int expw[BT / 64];
+};
+
+// Lane (r, g) = (t % 128, t / 128) keeps row r of the columns c = g + 4j
+// (j < 32) in binary64 registers; the four column groups are whole waves, so
+// reads of v and w at a lane's columns are wave-wide broadcasts.  Step k:
+// the owner group of column k publishes it with the partial of ||x||^2 (one
+// barrier), every lane forms the reflector (Golub-Van Loan 8.3, as for n <=
+// 64), its partial of p = tau A v and of v^T A v (second barrier), p and w
+// (third barrier), then the rank-2 update A -= v w^T + w v^T of its entries.
+__global__ void __launch_bounds__(BT)
+k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restrict__ Qh, Ws ws)
+{
+    __shared__ RedSmem S;
+    const int64_t bi = blockIdx.x;
+    if (bi >= batch) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int r = t & (BN - 1), g = t >> 7;
+    const int s = n / 2, n1 = s, n2 = n - s;
+    const float *Ab = A + bi * n * n;
+
+    // load (coalesced, staged in LDS as binary32 over the reflector buffer)
+    float *St = reinterpret_cast<float *>(S.V);
+    constexpr int SLD = BN + 1;
+    for (int e = t; e < n * n; e += BT) St[(e / n) * SLD + e % n] = Ab[e];
+    __syncthreads();
+    double ar[CPL];
+    bool bad = false;
+    float amax = 0.f;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int c = g + 4 * j;
+        float v = 0.f;
+        if (r < n && c < n) {
+            v = (c <= r) ? St[r * SLD + c] : St[c * SLD + r];  // lower triangle
+            bad = bad || !f_finite(v);
+            amax = f_max(amax, f_abs(v));
+        }
+        ar[j] = double(v);
+    }
+    {
+        const bool wb = __ballot(bad) != 0;
+        const int we = group_max<64>(exp_field(amax), lane);
+        if (lane == 0) {
+            S.badw[wave] = wb ? 1 : 0;
+            S.expw[wave] = we;
+        }
+    }
+    __syncthreads();
+    int anybad = 0, emax = 0;
+#pragma unroll
+    for (int w = 0; w < BT / 64; ++w) {
+        anybad |= S.badw[w];
+        emax = max(emax, S.expw[w]);
+    }
+    // exact power-of-two scaling to max |a_ij| in [1/2, 1), as for n <= 64
+    int sh = (emax == 0) ? 0 : fexp<float>::BIAS - 1 - emax;
+    sh = min(max(sh, -fexp<float>::SMAX), fexp<float>::SMAX);
+    if (anybad) {
+        for (int e = t; e < n1 * n1; e += BT) ws.c1[bi * n1 * n1 + e] = 0.f;
+        for (int e = t; e < n2 * n2; e += BT) ws.c2[bi * n2 * n2 + e] = 0.f;
+        if (t == 0) ws.meta[bi] = Meta{0.f, 0, 1, 0};
+        return;
+    }
+    const double hs = double(fexp<float>::pow2(sh));
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) ar[j] *= hs;
+    __syncthreads();  // the staging buffer becomes the reflector store
+
+    for (int k = 0; k < n - 2; ++k) {
+        const int gk = k & 3, jk = k >> 2;
+        if (g == gk) {
+            const double x = pick<CPL>(ar, jk);
+            S.x[r] = (r > k && r < n) ? x : 0.0;
+            if (r == k) S.a[k] = float(x);
+            const double s2 = wave_sum_all((r > k + 1 && r < n) ? x * x : 0.0);
+            if (lane == 0) S.red[wave & 1] = s2;
+        }
+        __syncthreads();
+        const double x0 = S.x[k + 1];
+        const double sig = S.red[0] + S.red[1];
+        const HhRefl<double> h = hh_reflector<float>(x0, sig);
+        const bool nz = sig != 0.0;
+        const double vr = (r == k + 1) ? 1.0 : ((r > k + 1 && nz) ? S.x[r] * h.rv0 : 0.0);
+        double vc[CPL];
+        double pp = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int c = g + 4 * j;
+            vc[j] = (c == k + 1) ? 1.0 : ((c > k + 1 && nz) ? S.x[c] * h.rv0 : 0.0);
+            pp = fma(ar[j], vc[j], pp);
+        }
+        S.part[0][g][r] = pp;
+        const double pv = wave_sum_all(vr * pp);  // partial of v^T A v
+        if (lane == 0) S.red2[wave] = pv;
+        if (g == 0) S.V[k * BN + r] = vr;
+        if (t == 0) {
+            S.tau[k] = h.tau;
+            S.b[k] = float(h.alpha);
+        }
+        __syncthreads();
+        const double p = h.tau * (S.part[0][0][r] + S.part[0][1][r] + S.part[0][2][r] + S.part[0][3][r]);
+        double vav = 0.0;
+#pragma unroll
+        for (int w = 0; w < BT / 64; ++w) vav += S.red2[w];
+        const double ptv = h.tau * vav;  // p^T v = tau v^T A v
+        const double wr = (r > k) ? p - 0.5 * h.tau * ptv * vr : 0.0;
+        if (g == 0) S.w[r] = wr;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int c = g + 4 * j;
+            ar[j] = fma(-vr, S.w[c], fma(-wr, vc[j], ar[j]));
+        }
+    }
+    // last 2 x 2 block
+    {
+        const int c0 = n - 2, c1 = n - 1;
+        if (g == (c0 & 3)) {
+            const double x = pick<CPL>(ar, c0 >> 2);
+            if (r == c0) S.a[c0] = float(x);
+            if (r == c1) S.b[c0] = float(x);
+        }
+        if (g == (c1 & 3) && r == c1) S.a[c1] = float(pick<CPL>(ar, c1 >> 2));
+    }
+    __syncthreads();
+
+    // tear (Eq. (3)) and the two children, dense
+    {
+        const float beta = S.b[s - 1];
+        const float rho = f_abs(beta);
+        float *C1 = ws.c1 + bi * n1 * n1;
+        float *C2 = ws.c2 + bi * n2 * n2;
+        for (int e = t; e < n1 * n1; e += BT) {
+            const int i = e / n1, j = e % n1;
+            float v = 0.f;
+            if (i == j) v = S.a[i] - (i == s - 1 ? rho : 0.f);
+            else if (j == i + 1) v = S.b[i];
+            else if (i == j + 1) v = S.b[j];
+            C1[e] = v;
+        }
+        for (int e = t; e < n2 * n2; e += BT) {
+            const int i = e / n2, j = e % n2;
+            float v = 0.f;
+            if (i == j) v = S.a[s + i] - (i == 0 ? rho : 0.f);
+            else if (j == i + 1) v = S.b[s + i];
+            else if (i == j + 1) v = S.b[s + j];
+            C2[e] = v;
+        }
+        if (t == 0) ws.meta[bi] = Meta{beta, sh, 0, 0};
+    }
+    if (!Qh) return;
+
+    // Q_H = H_0 H_1 ... H_{n-3}: from the identity, H_k Q for k = n-3 .. 0.
+    // Lane (c, g) keeps column c of the rows g + 4j.
+    {
+        const int c = r;
+        double qr[CPL];
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) qr[j] = (g + 4 * j == c) ? 1.0 : 0.0;
+        for (int k = n - 3; k >= 0; --k) {
+            const double *vk = S.V + k * BN;
+            double y = 0.0;
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) y = fma(vk[g + 4 * j], qr[j], y);
+            S.part[k & 1][g][c] = y;
+            __syncthreads();
+            const int pb = k & 1;
+            const double yc = S.tau[k] * (S.part[pb][0][c] + S.part[pb][1][c] + S.part[pb][2][c] +
+                                          S.part[pb][3][c]);
+#pragma unroll
+            for (int j = 0; j < CPL; ++j) qr[j] = fma(-vk[g + 4 * j], yc, qr[j]);
+        }
+        float *Qb = Qh + bi * n * n;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int row = g + 4 * j;
+            if (row < n && c < n) Qb[row * n + c] = float(qr[j]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ top merge
+struct MrgSmem {
+    static constexpr int LD = BN + 1;  // odd stride; column BN is the padding column of M
+    float W[BN * LD];  // Q_H staged, then Q_H diag(Q1, Q2)
+    float M[BN * LD];  // diag(Q1, Q2) staged, then the merge matrix
+    struct {
+        MergeArrays<float, BN> m;
+    } u;
+    float lamc[BN];  // children's eigenvalues, D1 then D2
+    float lout[BN];  // eigenvalues, ascending
+    float zin[BN];
+    float red[4][2];
+    uint64_t live[2], dead[2];
+    int capped, anyrot, cand;
+};
+
+// One wave's 16-column tile of X = A B for the row tiles of an n x n product
+// held in LDS (zero padding up to the tile sizes), in accumulators.
+__device__ __forceinline__ void tile_product(const float *__restrict__ Am,
+                                             const float *__restrict__ Bm, const int n,
+                                             const int ct, const int lane, f32x4 (&acc)[BN / 16])
+{
+    using MF = Mf<float>;
+    constexpr int LD = MrgSmem::LD;
+    const int i16 = lane & 15, kk = lane >> 4;
+    const int c = 16 * ct + i16;
+    const int ks = (n + 3) >> 2;
+#pragma unroll
+    for (int rt = 0; rt < BN / 16; ++rt) acc[rt] = MF::zero();
+    for (int s4 = 0; s4 < ks; ++s4) {
+        const int k = 4 * s4 + kk;
+        const float bv = Bm[k * LD + c];
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt)
+            if (16 * rt < n) acc[rt] = MF::mma(Am[(16 * rt + i16) * LD + k], bv, acc[rt]);
+    }
+}
+
+__global__ void __launch_bounds__(BT)
+k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q,
+            int32_t *__restrict__ info, Ws ws)
+{
+    __shared__ MrgSmem S;
+    using MF = Mf<float>;
+    constexpr int LD = MrgSmem::LD;
+    const int64_t bi = blockIdx.x;
+    if (bi >= batch) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int s = n / 2, n1 = s, n2 = n - s;
+    const Meta md = ws.meta[bi];
+    float *Qb = Q ? Q + bi * n * n : nullptr;
+    if (md.bad) {
+        if (Qb)
+            for (int e = t; e < n * n; e += BT) Qb[e] = f_nan<float>();
+        for (int e = t; e < n; e += BT) lam[bi * n + e] = f_nan<float>();
+        if (t == 0 && info) info[bi] = -1;
+        return;
+    }
+    const float *Q1 = ws.q1 + bi * n1 * n1;
+    const float *Q2 = ws.q2 + bi * n2 * n2;
+    // diag(Q1, Q2) into M and Q_H into W, zero outside n x n
+    for (int e = t; e < BN * LD; e += BT) {
+        const int i = e / LD, j = e % LD;
+        float v = 0.f;
+        if (i < n1 && j < n1) v = Q1[i * n1 + j];
+        else if (i >= n1 && i < n && j >= n1 && j < n) v = Q2[(i - n1) * n2 + j - n1];
+        S.M[e] = v;
+        if (Qb) S.W[e] = (i < n && j < n) ? Qb[i * n + j] : 0.f;
+    }
+    for (int e = t; e < n; e += BT) S.lamc[e] = e < n1 ? ws.l1[bi * n1 + e] : ws.l2[bi * n2 + e - n1];
+    if (t == 0) {
+        S.capped = 0;
+        S.anyrot = 0;
+        S.cand = 0;
+    }
+    __syncthreads();
+    const float rho = f_abs(md.beta);
+    const float sgm = (md.beta < 0.f) ? -1.f : 1.f;
+    // z (Eq. (5)): sgn(beta) times the last row of Q1 over the first row of Q2
+    if (t < n) S.zin[t] = (t < n1) ? sgm * S.M[(n1 - 1) * LD + t] : S.M[n1 * LD + t];
+    f32x4 acc[BN / 16];
+    if (Qb && 16 * wave < n) tile_product(S.W, S.M, n, wave, lane, acc);
+    __syncthreads();
+    if (Qb && 16 * wave < n) {
+        const int c = 16 * wave + (lane & 15);
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt)
+            if (16 * rt < n)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) S.W[(16 * rt + MF::crow(lane, v)) * LD + c] = acc[rt][v];
+    }
+    // stable merge of the two ascending child lists
+    if (t < n) {
+        const float de = S.lamc[t], ze = S.zin[t];
+        const bool left = t < n1;
+        const int pos = (left ? t : t - n1) +
+                        count_below(S.lamc + (left ? n1 : 0), left ? n2 : n1, de, !left);
+        S.u.m.sd[pos] = de;
+        S.u.m.sz[pos] = ze;
+        S.u.m.sperm[pos] = t;
+    }
+    for (int e = t; e < BN * LD; e += BT) S.M[e] = 0.f;  // the merge matrix, zero padded
+    __syncthreads();
+
+    // ---- deflation (type 1: rho |z_i| <= tol; type 2: Givens rotation of a
+    // close pair), tol = 8u max(max |d|, rho z^T z), as for n <= 64 ----------
+    const bool act = t < n;
+    float dp = act ? S.u.m.sd[t] : 0.f, zp = act ? S.u.m.sz[t] : 0.f;
+    if (wave < 2) {
+        const float v0 = wave_total(zp * zp), v1 = wave_total(dp * zp * zp), v2 = wave_total(dp * dp);
+        if (lane == 0) {
+            S.red[0][wave] = v0;
+            S.red[1][wave] = v1;
+            S.red[2][wave] = v2;
+        }
+    }
+    __syncthreads();
+    const float zz0 = S.red[0][0] + S.red[0][1];
+    const float dz = S.red[1][0] + S.red[1][1];
+    const float d2 = S.red[2][0] + S.red[2][1];
+    const float dmax = f_max(f_abs(S.u.m.sd[0]), f_abs(S.u.m.sd[n - 1]));
+    const float u = fp<float>::u;
+    const float tol = 8.f * u * f_max(dmax, rho * zz0);
+    const float fro2 = d2 + 2.f * rho * dz + rho * rho * zz0 * zz0;  // ||node||_F^2 (Eq. (10))
+    bool defl = act && (rho * f_abs(zp) <= tol);
+    if (defl) zp = 0.f;
+    if (act) {
+        S.u.m.sdefl[t] = defl ? 1 : 0;
+        S.u.m.sz[t] = zp;
+        S.u.m.rpart[t] = -1;
+    }
+    {
+        const uint64_t lv = __ballot(act && !defl);
+        if (wave < 2 && lane == 0) S.live[wave] = lv;
+    }
+    __syncthreads();
+    // Pairs of consecutive live elements that may pass the type-2 test (with
+    // a factor 2 of slack for the different rounding of this test): if there
+    // is one, the exact sequential scan below runs.  Rotations only follow
+    // from passing pairs, so without a candidate nothing changes.
+    if (act && !defl) {
+        const uint64_t l0 = S.live[0], l1 = S.live[1];
+        int prev = -1;
+        if (t >= 64) {
+            const uint64_t bl = l1 & lane_range(0, t - 64);
+            prev = bl ? 64 + 63 - __clzll(bl) : (l0 ? 63 - __clzll(l0) : -1);
+        } else {
+            const uint64_t bl = l0 & lane_range(0, t);
+            prev = bl ? 63 - __clzll(bl) : -1;
+        }
+        if (prev >= 0) {
+            const float zpr = S.u.m.sz[prev], dpr = S.u.m.sd[prev];
+            const float rr = f_hypot(zpr, zp);
+            if (f_abs((dp - dpr) * (zp / rr) * (zpr / rr)) <= 2.f * tol) S.cand = 1;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        int nr = 0;
+        if (S.cand) {
+            // consecutive live pairs (last, p) in ascending order; a passing
+            // pair is rotated, `last` deflates and p carries on
+            int last = -1;
+            for (int p = 0; p < n; ++p) {
+                if (S.u.m.sdefl[p]) continue;
+                if (last >= 0) {
+                    const float zl = S.u.m.sz[last], zi = S.u.m.sz[p];
+                    const float dl = S.u.m.sd[last], di = S.u.m.sd[p];
+                    const float rr = f_hypot(zl, zi);
+                    const float c = zi / rr, sn = zl / rr;
+                    if (f_abs((di - dl) * c * sn) <= tol) {
+                        S.u.m.sd[last] = dl * c * c + di * sn * sn;
+                        S.u.m.sd[p] = dl * sn * sn + di * c * c;
+                        S.u.m.sz[last] = 0.f;
+                        S.u.m.sz[p] = rr;
+                        S.u.m.sdefl[last] = 1;
+                        S.u.m.rc[last] = c;
+                        S.u.m.rs[last] = sn;
+                        S.u.m.rpart[last] = p;
+                        S.u.m.rlist[nr++] = last;
+                    }
+                }
+                last = p;
+            }
+        }
+        S.u.m.nrot[0] = nr;
+        S.anyrot = nr > 0 ? 1 : 0;
+    }
+    __syncthreads();
+    // compaction: non-deflated (poles, weights, child-order rows) first, then
+    // the deflated items
+    if (act) {
+        dp = S.u.m.sd[t];
+        zp = S.u.m.sz[t];
+        defl = S.u.m.sdefl[t] != 0;
+    }
+    {
+        const uint64_t lv = __ballot(act && !defl), dv = __ballot(act && defl);
+        if (wave < 2 && lane == 0) {
+            S.live[wave] = lv;
+            S.dead[wave] = dv;
+        }
+        if (wave < 2) {
+            const float zz = wave_total((act && !defl) ? zp * zp : 0.f);
+            if (lane == 0) S.red[3][wave] = zz;
+        }
+    }
+    __syncthreads();
+    const uint64_t L0 = S.live[0], L1 = S.live[1], D0 = S.dead[0], D1 = S.dead[1];
+    const int k = __popcll(L0) + __popcll(L1);
+    if (act) {
+        const int row = S.u.m.sperm[t];
+        if (!defl) {
+            const int idx = (t < 64) ? __popcll(L0 & lane_range(0, t))
+                                     : __popcll(L0) + __popcll(L1 & lane_range(0, t - 64));
+            S.u.m.dk[idx] = dp;
+            S.u.m.zk[idx] = zp;
+            S.u.m.ndrow[idx] = row;
+        } else {
+            const int idx = k + ((t < 64) ? __popcll(D0 & lane_range(0, t))
+                                          : __popcll(D0) + __popcll(D1 & lane_range(0, t - 64)));
+            S.u.m.itv[idx] = dp;
+            S.u.m.itrow[idx] = row;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        S.u.m.nk[0] = k;
+        S.u.m.nrho[0] = rho;
+        S.u.m.nzz[0] = S.red[3][0] + S.red[3][1];
+        S.u.m.nfro[0] = f_sqrt(f_max(fro2, 0.f));
+    }
+    __syncthreads();
+
+    // ---- secular roots, Loewner vectors, merge matrix (one node, depth 0) --
+    roots_vectors<float, BN, BT, BN / (BT / BN)>(S, n, 0, t, S.lout, BN / 2);
+
+    // ---- Q = W M with the sign rule, eigenvalues, info ---------------------
+    if (Qb && 16 * wave < n) {
+        tile_product(S.W, S.M, n, wave, lane, acc);
+        const int c = 16 * wave + (lane & 15);
+        float best = -1.f, bval = 0.f;
+        int brow = 1 << 20;
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt) {
+            if (16 * rt >= n) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rt + MF::crow(lane, v);
+                const float av = f_abs(acc[rt][v]);
+                const bool take = row < n && (av > best || (av == best && row < brow));
+                best = take ? av : best;
+                brow = take ? row : brow;
+                bval = take ? acc[rt][v] : bval;
+            }
+        }
+        {
+            const float ob = xmove<16>(best, lane);
+            const int orow = xmove<16>(brow, lane);
+            const float oval = xmove<16>(bval, lane);
+            const bool take = ob > best || (ob == best && orow < brow);
+            best = take ? ob : best;
+            brow = take ? orow : brow;
+            bval = take ? oval : bval;
+        }
+        {
+            const float ob = xmove<32>(best, lane);
+            const int orow = xmove<32>(brow, lane);
+            const float oval = xmove<32>(bval, lane);
+            const bool take = ob > best || (ob == best && orow < brow);
+            bval = take ? oval : bval;
+        }
+        const float sgn = (bval < 0.f) ? -1.f : 1.f;
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt) {
+            if (16 * rt >= n) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rt + MF::crow(lane, v);
+                if (row < n && c < n) Qb[row * n + c] = sgn * acc[rt][v];
+            }
+        }
+    }
+    const float unscale = fexp<float>::pow2(-md.shift);
+    for (int e = t; e < n; e += BT) lam[bi * n + e] = unscale * S.lout[e];
+    if (t == 0 && info) info[bi] = S.capped + ws.i1[bi] + ws.i2[bi];
+}
+
+// ------------------------------------------------------------------ host
+// One workspace per stream (grown on demand; a buffer in use by a captured
+// graph is pinned and never freed).
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_mu;
+Lru<void *, Buf> g_bufs(8);
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace big
+
+bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *lam, void *Q,
+                     int32_t *info, hipStream_t s)
+{
+    using namespace big;
+    if (dt != BED_F32)
+        return fail(BED_ERR_UNSUPPORTED, "n = %d > 64 is supported in binary32 only", n);
+    if (n <= 64 || n > BN) return fail(BED_ERR_INVALID_ARG, "big_solve: n = %d", n);
+    const int n1 = n / 2, n2 = n - n1;
+    const size_t B = (size_t)batch;
+    // children contiguous per kind: c1 then c2, q1 then q2, l1 then l2, i1 then i2
+    const size_t c_bytes = align_up(B * (n1 * n1 + n2 * n2) * sizeof(float));
+    const size_t l_bytes = align_up(B * n * sizeof(float));
+    const size_t i_bytes = align_up(2 * B * sizeof(int32_t));
+    const size_t m_bytes = align_up(B * sizeof(Meta));
+    const size_t need = 2 * c_bytes + l_bytes + i_bytes + m_bytes;
+    const bool capturing = stream_capturing(s);
+    char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        Buf *b = g_bufs.find((void *)s);
+        if (!b || b->bytes < need) {
+            if (capturing)
+                return fail(BED_ERR_CAPTURE, "workspace for n > 64 would be allocated during capture");
+            if (b) {
+                hipError_t e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+                (void)hipFree(b->ptr);
+                b->ptr = nullptr;
+                b->bytes = 0;
+                e = hipMalloc(&b->ptr, need);
+                if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+                b->bytes = need;
+            } else {
+                Buf nb;
+                hipError_t e = hipMalloc(&nb.ptr, need);
+                if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+                nb.bytes = need;
+                std::vector<Buf> old = g_bufs.insert((void *)s, nb);
+                if (!old.empty()) {
+                    (void)hipDeviceSynchronize();  // their last uses were on other streams
+                    for (Buf &o : old) (void)hipFree(o.ptr);
+                }
+                b = g_bufs.find((void *)s);
+            }
+        }
+        if (capturing) g_bufs.pin((void *)s);
+        base = (char *)b->ptr;
+    }
+    Ws ws;
+    ws.c1 = (float *)base;
+    ws.c2 = ws.c1 + B * n1 * n1;
+    ws.q1 = (float *)(base + c_bytes);
+    ws.q2 = ws.q1 + B * n1 * n1;
+    ws.l1 = (float *)(base + 2 * c_bytes);
+    ws.l2 = ws.l1 + B * n1;
+    ws.i1 = (int32_t *)(base + 2 * c_bytes + l_bytes);
+    ws.i2 = ws.i1 + B;
+    ws.meta = (Meta *)(base + 2 * c_bytes + l_bytes + i_bytes);
+
+    hipLaunchKernelGGL(k_big_reduce, dim3((unsigned)batch), dim3(BT), 0, s, (const float *)A, n,
+                       (int64_t)batch, (float *)Q, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_big_reduce launch");
+    const bed_tune dflt = default_tune();
+    if (n1 == n2) {
+        e = launch_uniform(BED_F32, class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1,
+                           ws.q1, ws.i1, s);
+    } else {
+        e = launch_uniform(BED_F32, class_shape(size_class(n1), dflt), ws.c1, n1, batch, ws.l1,
+                           ws.q1, ws.i1, s);
+        if (e == hipSuccess)
+            e = launch_uniform(BED_F32, class_shape(size_class(n2), dflt), ws.c2, n2, batch, ws.l2,
+                               ws.q2, ws.i2, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "child solve launch");
+    hipLaunchKernelGGL(k_big_merge, dim3((unsigned)batch), dim3(BT), 0, s, n, (int64_t)batch,
+                       (float *)lam, (float *)Q, info, ws);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "k_big_merge launch");
+    return BED_OK;
+}
+
+}  // namespace bed

@@ -14,7 +14,7 @@ namespace bed {
 bed_status fail(bed_status st, const char *fmt, ...);
 bed_status hip_fail(hipError_t e, const char *what);
 size_t dtype_size(bed_dtype dt);
-bed_status check_sizes(bed_dtype dt, int64_t batch, const int32_t *n);
+bed_status check_sizes(bed_dtype dt, int64_t batch, const int32_t *n, int nmax = 64);
 bed_status check_ptr(const void *p, bed_dtype dt, const char *name, bool nullable);
 bool stream_capturing(hipStream_t s);
 int device_cu_count();
@@ -28,6 +28,12 @@ bed_tune tuned_or_default(bed_dtype dt, int64_t batch, const int32_t *n);
 
 bed_status plan_run_impl(const bed_plan *p, const void *A, void *lam, void *Q, int32_t *info,
                          hipStream_t s);
+
+// Uniform batch of order 64 < n <= NMAX_BIG (binary32): reduction and tearing
+// kernel, the two halves on the n <= 64 kernels, top-merge kernel.  Q may be
+// NULL (eigenvalues only).
+bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *lam, void *Q,
+                     int32_t *info, hipStream_t s);
 
 // Runs `launch(items, count, nmax)` with the cached device work list of a
 // mixed-size batch (input order), recording its use on stream s.

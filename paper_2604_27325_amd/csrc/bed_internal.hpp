@@ -40,6 +40,10 @@ struct TeamShape {
 };
 inline bool leaf_supported(int leaf) { return leaf == 2 || leaf == 4 || leaf == 8; }
 
+// Largest order of the one-shot solve (64 < n <= NMAX_BIG: binary32, uniform
+// batches, one tearing step above the n <= 64 kernels).
+constexpr int NMAX_BIG = 128;
+
 bool team_supported(bed_dtype dt, TeamShape ts);
 
 // One workgroup per matrix of a uniform batch.

@@ -84,6 +84,29 @@ template <typename T> struct HhArith {
     using type = double;
 };
 
+// Per-element state of the merges of one depth; arrays indexed by global
+// position (node-local at [lo, hi)).
+template <typename T, int NMAX>
+struct MergeArrays {
+    T sd[NMAX], sz[NMAX];     // sorted poles / weights (deflation in place)
+    int sperm[NMAX], sdefl[NMAX];
+    T dk[NMAX], zk[NMAX];     // non-deflated poles / weights at [lo, lo + k)
+    int ndrow[NMAX];          // child-order row of non-deflated component
+    int itrow[NMAX];          // child-order row of deflated item at [lo + k, hi)
+    T itv[NMAX];              // item values: roots at [lo, lo+k), deflated after
+    T rtau[NMAX], rdo[NMAX];  // root offset and its origin pole value
+    T zh[NMAX];
+    T rc[NMAX], rs[NMAX];
+    int rpart[NMAX];
+    int rlist[NMAX], nrot[NMAX];  // per node: deflated index of each rotation, in scan order
+    int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
+    int ckl[NMAX], ckh[NMAX];  // child block of each row (its own block for an unmerged leaf)
+    int tklo[NMAX / 16], tkhi[NMAX / 16];  // per 16-row tile: K range of the product
+    int tnlo[NMAX / 16], tnhi[NMAX / 16];  // per 16-row tile: span of its nodes
+    int nk[NMAX];
+    T nrho[NMAX], nzz[NMAX], nfro[NMAX];
+};
+
 template <typename T, int NMAX, int NT>
 struct Smem {
     static constexpr int LD = NMAX + 1;  // odd row stride: column walks hit distinct banks
@@ -109,25 +132,7 @@ struct Smem {
             alignas(16) H vbuf[HW * NMAX];
             alignas(16) H wbuf[HW * NMAX];
         } h;
-        struct {  // merges; arrays indexed by global position (node-local at [lo, hi))
-            T sd[NMAX], sz[NMAX];     // sorted poles / weights (deflation in place)
-            int sperm[NMAX], sdefl[NMAX];
-            T dk[NMAX], zk[NMAX];     // non-deflated poles / weights at [lo, lo + k)
-            int ndrow[NMAX];          // child-order row of non-deflated component
-            int itrow[NMAX];          // child-order row of deflated item at [lo + k, hi)
-            T itv[NMAX];              // item values: roots at [lo, lo+k), deflated after
-            T rtau[NMAX], rdo[NMAX];  // root offset and its origin pole value
-            T zh[NMAX];
-            T rc[NMAX], rs[NMAX];
-            int rpart[NMAX];
-            int rlist[NMAX], nrot[NMAX];  // per node: deflated index of each rotation, in scan order
-            int nlo[NMAX], nhi[NMAX];  // node of each element at this depth
-            int ckl[NMAX], ckh[NMAX];  // child block of each row (its own block for an unmerged leaf)
-            int tklo[NMAX / 16], tkhi[NMAX / 16];  // per 16-row tile: K range of the product
-            int tnlo[NMAX / 16], tnhi[NMAX / 16];  // per 16-row tile: span of its nodes
-            int nk[NMAX];
-            T nrho[NMAX], nzz[NMAX], nfro[NMAX];
-        } m;
+        MergeArrays<T, NMAX> m;
         struct {  // back-transform: per block of 16 reflectors, Gram matrix and T factor
             // 16 x 16 tiles with row stride 17 (bank-conflict free column reads)
             T gram[((NMAX + 13) / 16) * 272];
@@ -410,9 +415,9 @@ __device__ __forceinline__ T pick(const T* a, int idx)
 // KPL poles per lane in registers.  Threads [0, NMAX SL) take part (whole
 // waves); the per-root bracket and Halley logic runs on every lane of a root,
 // so fewer lanes per root cost less issue time than they add in sums.
-template <typename T, int NMAX, int NT, int SL, int KPL>
-__device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n, const int d,
-                                              const int t, const int leaf)
+template <typename T, int NMAX, int NT, int SL, int KPL, typename SM>
+__device__ __forceinline__ void secular_roots(SM& S, const int n, const int d, const int t,
+                                              const int leaf)
 {
     constexpr int LPR = SL;
     const int lane = t & 63;
@@ -593,11 +598,11 @@ __device__ __forceinline__ void secular_roots(Smem<T, NMAX, NT>& S, const int n,
 // Merge phases M2-M5 of one depth with KPL poles (or items) per lane held in
 // registers: secular roots, Loewner zhat, eigenvector norms and output order,
 // merge-matrix assembly (incl. type-2 rotations).  All team threads call it.
-template <typename T, int NMAX, int NT, int KPL>
-__device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n, const int d,
-                                              const int t0, T* __restrict__ Ln, const int leaf)
+template <typename T, int NMAX, int NT, int KPL, typename SM>
+__device__ __forceinline__ void roots_vectors(SM& S, const int n, const int d, const int t0,
+                                              T* __restrict__ Ln, const int leaf)
 {
-    constexpr int LD = Smem<T, NMAX, NT>::LD;
+    constexpr int LD = SM::LD;
     constexpr int LPR = NT / NMAX;
     // opaque copy of the thread index: the lane addresses derived from it are
     // formed again at every depth rather than hoisted out of the depth loop
@@ -719,8 +724,8 @@ __device__ __forceinline__ void roots_vectors(Smem<T, NMAX, NT>& S, const int n,
 }
 
 // Calls roots_vectors with the smallest power-of-two KPL >= need.
-template <typename T, int NMAX, int NT, int KPL>
-__device__ __forceinline__ void roots_vectors_dispatch(Smem<T, NMAX, NT>& S, const int n,
+template <typename T, int NMAX, int NT, int KPL, typename SM>
+__device__ __forceinline__ void roots_vectors_dispatch(SM& S, const int n,
                                                        const int d, const int t, T* Ln, int need,
                                                        const int leaf)
 {

@@ -58,7 +58,12 @@ def test_argument_validation_without_gpu(lib):
     lib.bed_last_error.restype = ctypes.c_char_p
     i32 = ctypes.c_int32
     n = (i32 * 3)(4, 65, 8)
-    assert lib.bed_syevd(0, ctypes.c_int64(3), n, None, None, None, None, None) == 2  # n > 64
+    assert lib.bed_syevd(0, ctypes.c_int64(3), n, None, None, None, None, None) == 2  # mixed, n > 64
+    n = (i32 * 2)(129, 129)
+    assert lib.bed_syevd(0, ctypes.c_int64(2), n, None, None, None, None, None) == 2  # n > 128
+    n = (i32 * 2)(100, 100)
+    assert lib.bed_syevd(1, ctypes.c_int64(2), n, None, None, None, None, None) == 2  # FP64 > 64
+    assert lib.bed_syevd(0, ctypes.c_int64(2), n, None, None, None, None, None) == 1  # NULL A
     n = (i32 * 2)(4, 0)
     assert lib.bed_syevd(0, ctypes.c_int64(2), n, None, None, None, None, None) == 1  # n < 1
     assert lib.bed_syevd(0, ctypes.c_int64(-1), n, None, None, None, None, None) == 1

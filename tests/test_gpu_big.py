@@ -1,0 +1,115 @@
+"""Orders 64 < n <= 128 (binary32, uniform batches): one tearing step above the
+n <= 64 kernels and the top merge on a 512-thread team, against the binary64
+oracle under the same parity rules as n <= 64."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_27325_amd import workloads
+from tests.parity import compare_batch
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2604_27325_amd as bed  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def check(A_np, label, vectors=True):
+    A = torch.from_numpy(np.ascontiguousarray(A_np)).to(DEV)
+    b, n = A_np.shape[0], A_np.shape[1]
+    print(f"[{label}] batch {b} n={n} vectors={vectors}", flush=True)
+    lam, Q, info = bed.syevd_packed([n] * b, A.view(-1), want_vectors=vectors)
+    torch.cuda.synchronize()
+    lam = lam.view(b, n).cpu().numpy()
+    Q = Q.view(b, n, n).cpu().numpy() if vectors else None
+    lam_o, Q_o, _ = oracle.syevd(A_np.astype(np.float64))
+    worst, fails = compare_batch(A_np, lam, Q, lam_o, Q_o if vectors else None, np.float32,
+                                 info=info.cpu().numpy())
+    print(f"  worst {worst}", flush=True)
+    assert not fails, f"{label}: {len(fails)} failing matrices, first {fails[:3]}"
+
+
+@pytest.mark.parametrize("n", [65, 66, 80, 96, 97, 127, 128])
+def test_gaussian_and_covariance(n):
+    rng = np.random.default_rng(8000 + n)
+    A = np.concatenate([workloads.gaussian_sym(rng, 8, n), workloads.covariance(rng, 8, n)])
+    check(A.astype(np.float32), f"n={n}")
+
+
+@pytest.mark.parametrize("n", [65, 96, 128])
+def test_planted_pairs_deflate(n):
+    """Planted eigenvalue pairs 1e-6 apart (type-2 deflation at the top merge
+    or in the halves) and repeated eigenvalues."""
+    A, idx, _ = workloads.paper_scale(n, batch=64, planted_frac=0.5)
+    rng = np.random.default_rng(8100 + n)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    w = np.repeat(np.linspace(-1.0, 1.0, n // 4 + 1), 4)[:n]  # fourfold eigenvalues
+    rep = ((V * w) @ V.T).astype(np.float32)
+    check(np.concatenate([A[idx][:24], rep[None]]), f"planted n={n}")
+
+
+@pytest.mark.parametrize("n", [65, 100, 128])
+def test_eigenvalues_only(n):
+    rng = np.random.default_rng(8200 + n)
+    A = np.concatenate([workloads.gaussian_sym(rng, 8, n), workloads.covariance(rng, 8, n)])
+    check(A.astype(np.float32), f"eigenvalues n={n}", vectors=False)
+
+
+def test_full_batch_512_n128_sampled():
+    """The batch-512 n = 128 workload (the bench's shape), sampled outputs
+    against the oracle."""
+    A_np, _, _ = workloads.paper_scale(128)
+    A = torch.from_numpy(A_np).to(DEV)
+    lam, Q, info = bed.syevd(A, return_info=True)
+    torch.cuda.synchronize()
+    idx = np.linspace(0, 511, 16).astype(int)
+    lam_o, Q_o, _ = oracle.syevd(A_np[idx].astype(np.float64))
+    worst, fails = compare_batch(A_np[idx], lam.cpu().numpy()[idx], Q.cpu().numpy()[idx], lam_o,
+                                 Q_o, np.float32, info=info.cpu().numpy()[idx])
+    print(f"[batch 512 n=128] worst {worst}", flush=True)
+    assert not fails, fails[:3]
+    assert int(info.abs().sum()) == 0
+
+
+def test_workspace_grows_and_results_repeat():
+    """Calls of growing and shrinking size on one stream (the workspace is
+    reused or grown), each bitwise equal to a fresh call."""
+    rng = np.random.default_rng(8300)
+    outs = []
+    for n, b in ((70, 3), (128, 40), (90, 1), (128, 40)):
+        A = torch.from_numpy(workloads.gaussian_sym(rng, b, n).astype(np.float32)).to(DEV)
+        outs.append((A, bed.syevd(A)))
+    torch.cuda.synchronize()
+    l1, q1 = outs[1][1]
+    l3, q3 = outs[3][1]
+    assert not torch.equal(outs[1][0], outs[3][0]) or (torch.equal(l1, l3) and torch.equal(q1, q3))
+    for A, (lam, Q) in outs:
+        l2, q2 = bed.syevd(A)
+        assert torch.equal(lam, l2) and torch.equal(Q, q2)
+
+
+def test_nonfinite_input_reports_info_minus_one():
+    rng = np.random.default_rng(8400)
+    A_np = workloads.gaussian_sym(rng, 3, 100).astype(np.float32)
+    A_np[1, 50, 7] = np.nan
+    A = torch.from_numpy(A_np).to(DEV)
+    lam, Q, info = bed.syevd(A, return_info=True)
+    info = info.cpu().numpy()
+    assert list(info) == [0, -1, 0]
+    assert torch.isnan(lam[1]).all() and torch.isnan(Q[1]).all()
+    assert torch.isfinite(lam[0]).all() and torch.isfinite(Q[2]).all()
+
+
+def test_unsupported_forms_fail_loudly():
+    A = torch.zeros(2, 100, 100, dtype=torch.float64, device=DEV)
+    with pytest.raises(bed.BedError) as ei:
+        bed.syevd(A)
+    assert ei.value.status == 2  # BED_ERR_UNSUPPORTED (binary64 above 64)
+    flat = torch.zeros(100 * 100 + 10 * 10, device=DEV)
+    with pytest.raises(bed.BedError) as ei:
+        bed.syevd_packed([100, 10], flat)
+    assert ei.value.status == 2  # mixed batch with n > 64
