@@ -88,7 +88,8 @@ k_syevd_ptrlist(const PtrItem *__restrict__ items, int count, int leaf)
 }
 
 // ---------------------------------------------------------------- dispatch
-#define BED_SHAPES(X) X(16, 64) X(32, 64) X(32, 128) X(64, 64) X(64, 128) X(64, 256) X(64, 512)
+#define BED_SHAPES(X) \
+    X(16, 64) X(32, 64) X(32, 128) X(32, 256) X(64, 64) X(64, 128) X(64, 256) X(64, 512)
 
 bool team_supported(bed_dtype dt, TeamShape ts)
 {

@@ -66,7 +66,7 @@ k_probe_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
                             threadIdx.x, leaf_default(NMAX));
 }
 
-#define BED_PROBE_SHAPES(X) X(16, 64) X(32, 64) X(32, 128) X(64, 256) X(64, 512)
+#define BED_PROBE_SHAPES(X) X(16, 64) X(32, 64) X(32, 128) X(32, 256) X(64, 256) X(64, 512)
 
 template <typename T>
 static hipError_t probe_t(int nt, const void *A, int n, int64_t batch, void *lam, void *Q,

@@ -52,8 +52,11 @@ namespace bed {
 
 // Waves that run the Householder reduction of a team: the row block of a
 // wave (NMAX^2/(64 HW) registers per lane) must fit the register budget.
+// n <= 32 takes two reducing waves in a team of four or more (the other two
+// form Q_H), one otherwise.
 #ifndef BED_HH_WAVES
-#define BED_HH_WAVES(T, NMAX, NT) ((NMAX) == 64 ? ((NT) / 64 < 4 ? (NT) / 64 : 4) : 1)
+#define BED_HH_WAVES(T, NMAX, NT) \
+    ((NMAX) == 64 ? ((NT) / 64 < 4 ? (NT) / 64 : 4) : (((NMAX) == 32 && (NT) >= 256) ? 2 : 1))
 #endif
 template <typename T, int NMAX, int NT> struct HH_WAVES {
     static constexpr int value = BED_HH_WAVES(T, NMAX, NT);
@@ -1321,10 +1324,13 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
             const T zpr = __shfl(zp, prev), dpr = __shfl(dp, prev);
             bool cand = false;
             if (act && !defl && prev != e) {
-                // |z| >= tol/rho here (no under/overflow in the squares); the
-                // sequential scan below recomputes passing pairs exactly
+                // |z| >= tol/rho here (no under/overflow in the squares).  This
+                // test rounds differently from the exact one of the scan below
+                // (reciprocal square root against hypot and division), so it
+                // allows a factor 2: every pair that passes the exact test is
+                // a candidate, and the scan decides each candidate exactly.
                 const T ir = f_rcp(f_sqrt(fma(zpr, zpr, zp * zp)));
-                cand = f_abs((dp - dpr) * (zp * ir) * (zpr * ir)) <= tol;
+                cand = f_abs((dp - dpr) * (zp * ir) * (zpr * ir)) <= T(2) * tol;
             }
             const uint64_t cmask = __ballot(cand);
             BED_MARK(d, 12);
@@ -1343,10 +1349,11 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
                 if (mine) {
                     // The scan over consecutive live pairs (last, p) changes
                     // something only at a pair that passes the test.  A pair
-                    // whose `last` no rotation has touched passes exactly when
-                    // the candidate test above (same operands, same formula)
-                    // did, so only candidates and the successor of each rotated
-                    // element are visited, in ascending order.
+                    // whose `last` no rotation has touched and that is not a
+                    // candidate fails it (the candidate test is looser), so
+                    // only candidates and the successor of each rotated
+                    // element are visited, in ascending order, each decided
+                    // by the exact test: the decisions of the full scan.
                     uint64_t lv = live & lane_range(lo, hi);
                     uint64_t cm = cmask & lane_range(lo, hi);
                     int mod = -1;  // element changed by the latest rotation

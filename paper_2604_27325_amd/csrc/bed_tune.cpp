@@ -117,7 +117,7 @@ extern "C" bed_status bed_autotune(bed_dtype dt, int64_t batch, const int32_t *n
     if (stream_capturing(s)) return fail(BED_ERR_CAPTURE, "autotune during stream capture");
     std::vector<bed_tune> cands;
     for (int tb : {128, 256, 512})
-        for (int tm : {64, 128})
+        for (int tm : {64, 128, 256})
             for (int pers : {0, 1}) {
                 bed_tune t;
                 t.threads_big = tb;

@@ -105,7 +105,7 @@ def test_autotune_returns_valid_schedule(uneven):
     lam = torch.empty(int(np.sum(ns)), device=DEV)
     Q = torch.empty_like(A)
     t = bed.autotune(torch.float32, ns, A, lam, Q)
-    assert t["threads_big"] in (128, 256, 512) and t["threads_mid"] in (64, 128)
+    assert t["threads_big"] in (128, 256, 512) and t["threads_mid"] in (64, 128, 256)
     assert t["leaf"] in (0, 2, 4, 8)
     plan = bed.Plan(torch.float32, ns, tune=t)
     l2, q2, info = run_plan(plan, ns, A)
@@ -125,7 +125,7 @@ def test_plan_create_refused_during_capture(uneven):
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
-@pytest.mark.parametrize("big,mid", [(64, 64), (128, 128), (256, 64), (512, 128)])
+@pytest.mark.parametrize("big,mid", [(64, 64), (128, 128), (256, 64), (512, 128), (512, 256)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
     """Every team shape (threads per matrix of the n > 32 and 16 < n <= 32
@@ -165,7 +165,7 @@ def test_every_team_shape_matches_oracle(dtype, big, mid, persistent):
 
 
 @pytest.mark.parametrize("leaf", [2, 4, 8])
-@pytest.mark.parametrize("big,mid", [(512, 128), (128, 64)])
+@pytest.mark.parametrize("big,mid", [(512, 128), (128, 64), (256, 256)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_leaf_cutoff_variants_match_oracle(dtype, big, mid, leaf):
     """Leaves of at most 2, 4 or 8 elements (Sec. 2.2), at every n from 1 to
