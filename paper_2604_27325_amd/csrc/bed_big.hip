@@ -131,6 +131,9 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     for (int j = 0; j < CPL; ++j) ar[j] *= hs;
     __syncthreads();  // the staging buffer becomes the reflector store
 
+    const int gs = __builtin_amdgcn_readfirstlane(g);
+    const int rhi = __builtin_amdgcn_readfirstlane((wave & 1) * 64 + 63);  // the wave's last row
+    auto wlive = [&](const int k) { return rhi > k; };
     for (int k = 0; k < n - 2; ++k) {
         const int gk = k & 3, jk = k >> 2;
         if (g == gk) {
@@ -144,17 +147,30 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         const double x0 = S.x[k + 1];
         const double sig = S.red[0] + S.red[1];
         const HhRefl<double> h = hh_reflector<float>(x0, sig);
-        const bool nz = sig != 0.0;
-        const double vr = (r == k + 1) ? 1.0 : ((r > k + 1 && nz) ? S.x[r] * h.rv0 : 0.0);
+        // v = (1, x_{k+2..} rv0): x is zero at rows <= k, and past k+1 too
+        // when sig = 0, so the scaled pivot column gives v without tests
+        const double vr = (r == k + 1) ? 1.0 : S.x[r] * h.rv0;
+        // Dead work is skipped by wave-uniform branches: chunks of eight of a
+        // lane's columns that lie at or left of column k (v is zero there and
+        // the columns are never read again), and whole waves whose rows are
+        // all <= k (their p and w are not used).
         double vc[CPL];
         double pp = 0.0;
+        if (wlive(k)) {
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const int c = g + 4 * j;
-            vc[j] = (c == k + 1) ? 1.0 : ((c > k + 1 && nz) ? S.x[c] * h.rv0 : 0.0);
-            pp = fma(ar[j], vc[j], pp);
+            for (int q = 0; q < CPL / 8; ++q) {
+                if (gs + 32 * q + 28 <= k) continue;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = 8 * q + jj;
+                    const int c = g + 4 * j;
+                    const double xc = S.x[c];
+                    vc[j] = (c == k + 1) ? 1.0 : xc * h.rv0;
+                    pp = fma(ar[j], vc[j], pp);
+                }
+            }
+            S.part[0][g][r] = pp;
         }
-        S.part[0][g][r] = pp;
         const double pv = wave_sum_all(vr * pp);  // partial of v^T A v
         if (lane == 0) S.red2[wave] = pv;
         if (g == 0) S.V[k * BN + r] = vr;
@@ -171,10 +187,17 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         const double wr = (r > k) ? p - 0.5 * h.tau * ptv * vr : 0.0;
         if (g == 0) S.w[r] = wr;
         __syncthreads();
+        if (wlive(k)) {
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const int c = g + 4 * j;
-            ar[j] = fma(-vr, S.w[c], fma(-wr, vc[j], ar[j]));
+            for (int q = 0; q < CPL / 8; ++q) {
+                if (gs + 32 * q + 28 <= k) continue;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = 8 * q + jj;
+                    const int c = g + 4 * j;
+                    ar[j] = fma(-vr, S.w[c], fma(-wr, vc[j], ar[j]));
+                }
+            }
         }
     }
     // last 2 x 2 block
@@ -224,16 +247,28 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         for (int j = 0; j < CPL; ++j) qr[j] = (g + 4 * j == c) ? 1.0 : 0.0;
         for (int k = n - 3; k >= 0; --k) {
             const double *vk = S.V + k * BN;
+            // rows <= k: v_k is zero there (chunks of eight rows skipped)
             double y = 0.0;
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) y = fma(vk[g + 4 * j], qr[j], y);
+            for (int q = 0; q < CPL / 8; ++q) {
+                if (gs + 32 * q + 28 <= k) continue;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) y = fma(vk[g + 4 * (8 * q + jj)], qr[8 * q + jj], y);
+            }
             S.part[k & 1][g][c] = y;
             __syncthreads();
             const int pb = k & 1;
             const double yc = S.tau[k] * (S.part[pb][0][c] + S.part[pb][1][c] + S.part[pb][2][c] +
                                           S.part[pb][3][c]);
 #pragma unroll
-            for (int j = 0; j < CPL; ++j) qr[j] = fma(-vk[g + 4 * j], yc, qr[j]);
+            for (int q = 0; q < CPL / 8; ++q) {
+                if (gs + 32 * q + 28 <= k) continue;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int j = 8 * q + jj;
+                    qr[j] = fma(-vk[g + 4 * j], yc, qr[j]);
+                }
+            }
         }
         float *Qb = Qh + bi * n * n;
 #pragma unroll

@@ -207,12 +207,15 @@ __device__ __forceinline__ void jacobi_rot(const T app, const T aqq, const T apq
     s = rot ? tt * cc : T(0);
 }
 
-// Value of lane ^ K inside aligned groups of 8 lanes: quad-permute DPP for K
-// < 4, a lane shuffle otherwise.
+// Value of lane ^ K inside aligned groups of 8 lanes, by DPP: a quad permute
+// for K < 4; for K >= 4 the half-row mirror (lane ^ 7 within 8), followed by
+// the quad permute of K ^ 7 when K < 7 -- lane i then reads lane (i ^ (K ^ 7))
+// ^ 7 = i ^ K.
 template <int K, typename T> __device__ __forceinline__ T lxor(T x)
 {
     if constexpr (K < 4) return qxor<K>(x);
-    else return __shfl_xor(x, K);
+    else if constexpr (K == 7) return xmove<4>(x, 0);
+    else return qxor<K ^ 7>(xmove<4>(x, 0));
 }
 
 // f(integral_constant<int, K>) for K = B, ..., E - 1 (compile-time indices).
