@@ -593,6 +593,17 @@ def main():
                          "launch_us_p90": float(np.percentile(each, 90) * 1e3)}
         print(f"[bench] n={n}: {per_n[str(n)]['eigendecomps_per_s']:.4g} matrices/s, "
               f"kernel {ev * 1e3:.1f} us", flush=True)
+        if n == 64:
+            # the same solve with one team per CU (batch = number of CUs): one
+            # matrix's chain latency with nothing sharing its CU
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            A1 = A[:cus].contiguous()
+            _, ev1, each1, _, _, _ = time_solver(bed, torch, A1, args.steps, args.warmup)
+            per_n[str(n)]["one_team_per_cu"] = {
+                "batch": cus, "kernel_ms": ev1,
+                "launch_us_median": float(np.median(each1) * 1e3),
+                "batch_512_over_this": float(np.median(each) / np.median(each1))}
+            print(f"[bench] n=64 one team per CU (batch {cus}): {ev1 * 1e3:.1f} us", flush=True)
         if n == sizes[-1]:
             main_res = (n, A_np, wall, ev, lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy())
 

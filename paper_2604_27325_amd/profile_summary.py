@@ -2,7 +2,8 @@
 profiles/ (measurement tool; reads profiler output, runs nothing on the GPU).
 
 Inputs: the kernel statistics of a kernel-trace run (--trace, a
-*_kernel_stats.csv) and a directory of counter runs (--pmc-dir, files
+*_kernel_stats.csv, or the per-dispatch *_kernel_trace.csv when --grid picks
+one launch shape) and a directory of counter runs (--pmc-dir, files
 p<i>_counter_collection.csv, one counter set per run).  FETCH_SIZE and
 WRITE_SIZE are calibrated against the device copy that `bench.py
 --copy-calibration` launches in the same process (--calib-bytes bytes read and
@@ -29,7 +30,17 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def trace_stats(path, kernel):
+def trace_stats(path, kernel, grid=None):
+    """Launch count and mean/min/max duration of `kernel`: from a kernel-stats
+    file, or from a per-dispatch kernel-trace file, where `grid` (work-items)
+    selects the dispatches of one launch shape."""
+    if "kernel_trace" in os.path.basename(path):
+        d = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in csv.DictReader(open(path))
+             if kernel in r["Kernel_Name"] and (grid is None or int(r["Grid_Size_X"]) == grid)]
+        if not d:
+            raise SystemExit(f"{kernel} (grid {grid}) not in {path}")
+        return {"calls": len(d), "avg_ns": sum(d) / len(d), "min_ns": float(min(d)),
+                "max_ns": float(max(d))}
     for r in csv.DictReader(open(path)):
         if kernel in r["Name"]:
             return {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
@@ -37,14 +48,15 @@ def trace_stats(path, kernel):
     raise SystemExit(f"{kernel} not in {path}")
 
 
-def counters(pmc_dir, kernel, calib_kernel):
-    """{counter: mean value per dispatch of `kernel`}, per-dispatch durations (ns),
-    and the calibration kernel's FETCH/WRITE values (largest dispatch)."""
+def counters(pmc_dir, kernel, calib_kernel, grid=None):
+    """{counter: mean value per dispatch of `kernel`} (only dispatches of `grid`
+    work-items when given), per-dispatch durations (ns), and the calibration
+    kernel's FETCH/WRITE values (largest dispatch)."""
     vals, durs, calib = defaultdict(list), defaultdict(list), {}
     for f in sorted(glob.glob(os.path.join(pmc_dir, "p*_counter_collection.csv"))):
         for r in csv.DictReader(open(f)):
             name, v = r["Counter_Name"], float(r["Counter_Value"])
-            if kernel in r["Kernel_Name"]:
+            if kernel in r["Kernel_Name"] and (grid is None or int(r["Grid_Size"]) == grid):
                 vals[name].append(v)
                 durs[name].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
             elif calib_kernel and calib_kernel in r["Kernel_Name"] and name in ("FETCH_SIZE",
@@ -73,6 +85,8 @@ def main():
     ap.add_argument("--calib-dir", default=None,
                     help="counter runs holding the calibration copy (default: --pmc-dir)")
     ap.add_argument("--calib-bytes", type=float, default=256 * 2 ** 20)
+    ap.add_argument("--grid", type=int, default=None,
+                    help="only dispatches of this many work-items (one launch shape)")
     ap.add_argument("--flops", type=float, required=True, help="algorithmic flops per launch")
     ap.add_argument("--bytes", type=float, required=True, help="algorithmic bytes per launch")
     ap.add_argument("--sources", nargs="+", required=True)
@@ -80,8 +94,8 @@ def main():
     ap.add_argument("--pmc-command", required=True)
     a = ap.parse_args()
 
-    tr = trace_stats(a.trace, a.kernel)
-    mean, vals, durs, calib = counters(a.pmc_dir, a.kernel, a.calib_kernel)
+    tr = trace_stats(a.trace, a.kernel, a.grid)
+    mean, vals, durs, calib = counters(a.pmc_dir, a.kernel, a.calib_kernel, a.grid)
     if a.calib_dir:
         calib = counters(a.calib_dir, "\0no kernel\0", a.calib_kernel)[3]
     xcc, fmax = gpu_agent(a.pmc_dir)
