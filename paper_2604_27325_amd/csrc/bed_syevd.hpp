@@ -2,16 +2,18 @@
 // eigendecomposition of one symmetric n x n matrix (n <= NMAX <= 64) held in
 // LDS/VGPRs:
 //
-//   load -> Householder tridiagonalization -> rank-one tearing (Sec. 2.1,
-//   Eq. (1)-(3)) -> 2x2 Givens leaves (Sec. 2.2) -> bottom-up merges (Sec. 2.3):
-//   z/sort (Eq. (4)-(5)), deflation, secular roots by hybrid-section + Halley
-//   under bounded interlacing (Eq. (8)-(21)), progressive removal of converged
-//   roots (Eq. (22)), Loewner eigenvectors (Eq. (23)-(25)), back-multiplication
-//   (Eq. (4)) -> Householder back-transform -> sign canonicalization -> store.
+//   load -> Householder tridiagonalization (binary64 arithmetic) -> rank-one
+//   tearing (Sec. 2.1, Eq. (1)-(3)) -> leaves of at most 2, 4 or 8 elements by
+//   cyclic Jacobi (Sec. 2.2) -> bottom-up merges (Sec. 2.3): z/sort (Eq.
+//   (4)-(5)), deflation, secular roots by hybrid-section + Halley under bounded
+//   interlacing (Eq. (8)-(21)), progressive removal of converged roots (Eq.
+//   (22)), Loewner eigenvectors (Eq. (23)-(25)), back-multiplication (Eq. (4))
+//   -> Householder back-transform -> sign canonicalization -> store.  Without
+//   eigenvectors the merges carry only the end rows of each node's block.
 //
 // Team geometry (NT threads, thread t):
-//   Householder / merge GEMM: row r = t % NMAX, column group g = t / NMAX,
-//     CPT = NMAX / G columns per thread (G = NT / NMAX groups).
+//   Householder: HW reducing waves, lane (r, g) holding row r of the columns
+//     g + G j (G = HW 64 / NMAX groups); the other waves form Q_H.
 //   Per-element phases: wave 0, lane e = element e (n <= 64 fits one wave).
 //   Per-root phases: root q = t / LPR, LPR = NT / NMAX lanes share one root's
 //     pole sums (aligned lane groups, butterfly reductions).
