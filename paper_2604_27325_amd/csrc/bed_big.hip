@@ -5,7 +5,8 @@
 // the n <= 64 solver laid out for 128 elements.
 //
 //   k_big_reduce  Householder tridiagonalization T = Q_H^T A Q_H with binary64
-//                 arithmetic (as for n <= 64); Q_H = H_0 ... H_{n-3} formed
+//                 arithmetic (binary32 for eigenvalues alone, as for n <= 64);
+//                 Q_H = H_0 ... H_{n-3} formed
 //                 explicitly and staged in the Q output; T torn at s =
 //                 floor(n/2) (Eq. (3)) into T1 (s x s) and T2 ((n-s) x (n-s)),
 //                 written as dense tridiagonal matrices
@@ -19,6 +20,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "bed_host.hpp"
 #include "bed_internal.hpp"
@@ -52,30 +54,33 @@ struct Ws {
 };
 
 // ------------------------------------------------------------------ reduction
+template <typename H>
 struct RedSmem {
-    double V[BN * BN];     // reflector v_k in row k (zero at rows <= k)
-    double x[BN];          // pivot column of the step
-    double w[BN];          // w = p - (tau/2)(p^T v) v
-    double part[2][4][BN]; // per column group: partial products
-    double red[8];         // per wave: partial sums
-    double red2[8];
-    double tau[BN];
+    H V[BN * BN];     // reflector v_k in row k (zero at rows <= k); load staging first
+    H x[BN];          // pivot column of the step
+    H w[BN];          // w = p - (tau/2)(p^T v) v
+    H part[2][4][BN]; // per column group: partial products
+    H red[8];         // per wave: partial sums
+    H red2[8];
+    H tau[BN];
     float a[BN], b[BN];
     int badw[BT / 64];
     int expw[BT / 64];
 };
 
-// Lane (r, g) = (t % 128, t / 128) keeps row r of the columns c = g + 4j
-// (j < 32) in binary64 registers; the four column groups are whole waves, so
+// Arithmetic type H: binary64 when Q_H is formed (eigenvectors), binary32
+// for eigenvalues alone (as for n <= 64).  Lane (r, g) = (t % 128, t / 128)
+// keeps row r of the columns c = g + 4j (j < 32) in registers; the four column groups are whole waves, so
 // reads of v and w at a lane's columns are wave-wide broadcasts.  Step k:
 // the owner group of column k publishes it with the partial of ||x||^2 (one
 // barrier), every lane forms the reflector (Golub-Van Loan 8.3, as for n <=
 // 64), its partial of p = tau A v and of v^T A v (second barrier), p and w
 // (third barrier), then the rank-2 update A -= v w^T + w v^T of its entries.
+template <typename H>
 __global__ void __launch_bounds__(BT)
 k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restrict__ Qh, Ws ws)
 {
-    __shared__ RedSmem S;
+    __shared__ RedSmem<H> S;
     const int64_t bi = blockIdx.x;
     if (bi >= batch) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -86,9 +91,10 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     // load (coalesced, staged in LDS as binary32 over the reflector buffer)
     float *St = reinterpret_cast<float *>(S.V);
     constexpr int SLD = BN + 1;
+    static_assert(sizeof(S.V) + sizeof(S.x) >= sizeof(float) * BN * SLD, "load staging");
     for (int e = t; e < n * n; e += BT) St[(e / n) * SLD + e % n] = Ab[e];
     __syncthreads();
-    double ar[CPL];
+    H ar[CPL];
     bool bad = false;
     float amax = 0.f;
 #pragma unroll
@@ -100,7 +106,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
             bad = bad || !f_finite(v);
             amax = f_max(amax, f_abs(v));
         }
-        ar[j] = double(v);
+        ar[j] = H(v);
     }
     {
         const bool wb = __ballot(bad) != 0;
@@ -126,7 +132,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         if (t == 0) ws.meta[bi] = Meta{0.f, 0, 1, 0};
         return;
     }
-    const double hs = double(fexp<float>::pow2(sh));
+    const H hs = H(fexp<float>::pow2(sh));
 #pragma unroll
     for (int j = 0; j < CPL; ++j) ar[j] *= hs;
     __syncthreads();  // the staging buffer becomes the reflector store
@@ -137,25 +143,25 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     for (int k = 0; k < n - 2; ++k) {
         const int gk = k & 3, jk = k >> 2;
         if (g == gk) {
-            const double x = pick<CPL>(ar, jk);
-            S.x[r] = (r > k && r < n) ? x : 0.0;
+            const H x = pick<CPL>(ar, jk);
+            S.x[r] = (r > k && r < n) ? x : H(0);
             if (r == k) S.a[k] = float(x);
-            const double s2 = wave_sum_all((r > k + 1 && r < n) ? x * x : 0.0);
+            const H s2 = wave_sum_all((r > k + 1 && r < n) ? x * x : H(0));
             if (lane == 0) S.red[wave & 1] = s2;
         }
         __syncthreads();
-        const double x0 = S.x[k + 1];
-        const double sig = S.red[0] + S.red[1];
-        const HhRefl<double> h = hh_reflector<float>(x0, sig);
+        const H x0 = S.x[k + 1];
+        const H sig = S.red[0] + S.red[1];
+        const HhRefl<H> h = hh_reflector<float>(x0, sig);
         // v = (1, x_{k+2..} rv0): x is zero at rows <= k, and past k+1 too
         // when sig = 0, so the scaled pivot column gives v without tests
-        const double vr = (r == k + 1) ? 1.0 : S.x[r] * h.rv0;
+        const H vr = (r == k + 1) ? H(1) : S.x[r] * h.rv0;
         // Dead work is skipped by wave-uniform branches: chunks of eight of a
         // lane's columns that lie at or left of column k (v is zero there and
         // the columns are never read again), and whole waves whose rows are
         // all <= k (their p and w are not used).
-        double vc[CPL];
-        double pp = 0.0;
+        H vc[CPL];
+        H pp = H(0);
         if (wlive(k)) {
 #pragma unroll
             for (int q = 0; q < CPL / 8; ++q) {
@@ -164,14 +170,14 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
                     const int c = g + 4 * j;
-                    const double xc = S.x[c];
-                    vc[j] = (c == k + 1) ? 1.0 : xc * h.rv0;
+                    const H xc = S.x[c];
+                    vc[j] = (c == k + 1) ? H(1) : xc * h.rv0;
                     pp = fma(ar[j], vc[j], pp);
                 }
             }
             S.part[0][g][r] = pp;
         }
-        const double pv = wave_sum_all(vr * pp);  // partial of v^T A v
+        const H pv = wave_sum_all(vr * pp);  // partial of v^T A v
         if (lane == 0) S.red2[wave] = pv;
         if (g == 0) S.V[k * BN + r] = vr;
         if (t == 0) {
@@ -179,12 +185,12 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
             S.b[k] = float(h.alpha);
         }
         __syncthreads();
-        const double p = h.tau * (S.part[0][0][r] + S.part[0][1][r] + S.part[0][2][r] + S.part[0][3][r]);
-        double vav = 0.0;
+        const H p = h.tau * (S.part[0][0][r] + S.part[0][1][r] + S.part[0][2][r] + S.part[0][3][r]);
+        H vav = H(0);
 #pragma unroll
         for (int w = 0; w < BT / 64; ++w) vav += S.red2[w];
-        const double ptv = h.tau * vav;  // p^T v = tau v^T A v
-        const double wr = (r > k) ? p - 0.5 * h.tau * ptv * vr : 0.0;
+        const H ptv = h.tau * vav;  // p^T v = tau v^T A v
+        const H wr = (r > k) ? p - H(0.5) * h.tau * ptv * vr : H(0);
         if (g == 0) S.w[r] = wr;
         __syncthreads();
         if (wlive(k)) {
@@ -204,7 +210,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     {
         const int c0 = n - 2, c1 = n - 1;
         if (g == (c0 & 3)) {
-            const double x = pick<CPL>(ar, c0 >> 2);
+            const H x = pick<CPL>(ar, c0 >> 2);
             if (r == c0) S.a[c0] = float(x);
             if (r == c1) S.b[c0] = float(x);
         }
@@ -237,18 +243,19 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         if (t == 0) ws.meta[bi] = Meta{beta, sh, 0, 0};
     }
     if (!Qh) return;
+    if constexpr (!std::is_same<H, double>::value) return;  // Q_H only with binary64
 
     // Q_H = H_0 H_1 ... H_{n-3}: from the identity, H_k Q for k = n-3 .. 0.
     // Lane (c, g) keeps column c of the rows g + 4j.
     {
         const int c = r;
-        double qr[CPL];
+        H qr[CPL];
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) qr[j] = (g + 4 * j == c) ? 1.0 : 0.0;
+        for (int j = 0; j < CPL; ++j) qr[j] = (g + 4 * j == c) ? H(1) : H(0);
         for (int k = n - 3; k >= 0; --k) {
-            const double *vk = S.V + k * BN;
+            const H *vk = S.V + k * BN;
             // rows <= k: v_k is zero there (chunks of eight rows skipped)
-            double y = 0.0;
+            H y = H(0);
 #pragma unroll
             for (int q = 0; q < CPL / 8; ++q) {
                 if (gs + 32 * q + 28 <= k) continue;
@@ -258,7 +265,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
             S.part[k & 1][g][c] = y;
             __syncthreads();
             const int pb = k & 1;
-            const double yc = S.tau[k] * (S.part[pb][0][c] + S.part[pb][1][c] + S.part[pb][2][c] +
+            const H yc = S.tau[k] * (S.part[pb][0][c] + S.part[pb][1][c] + S.part[pb][2][c] +
                                           S.part[pb][3][c]);
 #pragma unroll
             for (int q = 0; q < CPL / 8; ++q) {
@@ -640,8 +647,12 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     ws.i2 = ws.i1 + B;
     ws.meta = (Meta *)(base + 2 * c_bytes + l_bytes + i_bytes);
 
-    hipLaunchKernelGGL(k_big_reduce, dim3((unsigned)batch), dim3(BT), 0, s, (const float *)A, n,
-                       (int64_t)batch, (float *)Q, ws);
+    if (Q)
+        hipLaunchKernelGGL(k_big_reduce<double>, dim3((unsigned)batch), dim3(BT), 0, s,
+                           (const float *)A, n, (int64_t)batch, (float *)Q, ws);
+    else
+        hipLaunchKernelGGL(k_big_reduce<float>, dim3((unsigned)batch), dim3(BT), 0, s,
+                           (const float *)A, n, (int64_t)batch, (float *)nullptr, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_big_reduce launch");
     const bed_tune dflt = default_tune();

@@ -78,13 +78,14 @@ constexpr int QH_SYNC = 4;
 
 constexpr int SEC_CAP = 100;  // Halley-phase evaluations per root before "capped"
 
-// Arithmetic type of the Householder reduction.  Its rounding errors are a
-// backward error of A, which the eigenvalue differences and the eigenvectors
-// of close pairs amplify by 1/gap (the backward of the decomposition divides
-// by those differences).  In binary64 -- whose FMA issues at the rate of
-// unpacked binary32 on gfx950 -- they stay far below binary32's unit
-// roundoff; T, the reflectors and tau are then rounded once to the storage
-// type.
+// Arithmetic type of the Householder reduction when eigenvectors are formed.
+// Its rounding errors are a backward error of A, which the eigenvalue
+// differences and the eigenvectors of close pairs amplify by 1/gap (the
+// backward of the decomposition divides by those differences).  In binary64
+// -- whose FMA issues at the rate of unpacked binary32 on gfx950 -- they stay
+// far below binary32's unit roundoff; T, the reflectors and tau are then
+// rounded once to the storage type.  (The LDS buffers of the reduction are
+// sized for this type; a reduction in T uses them reinterpreted.)
 template <typename T> struct HhArith {
     using type = double;
 };
@@ -836,16 +837,11 @@ __device__ __forceinline__ HhRefl<H> hh_reflector(const H x0, const H sig)
     return h;
 }
 
-template <typename T, int NMAX, int NT, int HW, int Q0>
+template <typename T, int NMAX, int NT, int HW, int Q0, typename H>
 __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, const int lane,
-                                         const int wave,
-                                         typename HhArith<T>::type (&ar)[NMAX * NMAX / (64 * HW)],
-                                         typename HhArith<T>::type& xr,
-                                         typename HhArith<T>::type& sig,
-                                         typename HhArith<T>::type& vr,
-                                         typename HhArith<T>::type& tauk)
+                                         const int wave, H (&ar)[NMAX * NMAX / (64 * HW)], H& xr,
+                                         H& sig, H& vr, H& tauk)
 {
-    using H = typename HhArith<T>::type;
     constexpr int GW = 64 / NMAX;   // column groups per wave
     constexpr int G = HW * GW;      // column groups of the team
     constexpr int CPT = NMAX / G;
@@ -854,8 +850,9 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
     const int glast = wave * GW + GW - 1;  // last group of this wave
     const bool g0 = gl == 0;
     const int pos_r = (r % G) * CPT + r / G;
-    H* vb = S.u.h.vbuf + wave * NMAX;
-    H* wb = S.u.h.wbuf + wave * NMAX;
+    H* vb = reinterpret_cast<H*>(S.u.h.vbuf) + wave * NMAX;
+    H* wb = reinterpret_cast<H*>(S.u.h.wbuf) + wave * NMAX;
+    H* colb = reinterpret_cast<H*>(S.u.h.colb);
     // instance Q0 = NCH: every column of this wave is dead, but the wave
     // keeps stepping (barriers, pivot column, next reflector) until n - 2
     const int kb = (Q0 == 0) ? 0 : glast + G * (4 * Q0 - 1);
@@ -888,9 +885,9 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
         if constexpr (Q0 < NCH) a1 = pick<4>(ar + 4 * Q0, (c1 / G) & 3);
         H cb;
         if constexpr (HW > 1) {
-            H* pa = S.u.h.part + (k & 1) * HW * NMAX;
+            H* pa = reinterpret_cast<H*>(S.u.h.part) + (k & 1) * HW * NMAX;
             if (g0) pa[wave * NMAX + r] = pr;
-            if (g == g1) S.u.h.colb[(k & 1) * NMAX + r] = a1;
+            if (g == g1) colb[(k & 1) * NMAX + r] = a1;
             team_sync<NT>();
             H q[HW];
 #pragma unroll
@@ -900,7 +897,7 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
 #pragma unroll
                 for (int w2 = 0; w2 + st < HW; w2 += 2 * st) q[w2] += q[w2 + st];
             pr = q[0];
-            cb = S.u.h.colb[(k & 1) * NMAX + r];
+            cb = colb[(k & 1) * NMAX + r];
             BED_HSTEP(k, 2);
         } else {
             cb = a1;
@@ -959,7 +956,7 @@ __device__ __forceinline__ void hh_range(Smem<T, NMAX, NT>& S, const int n, cons
             if (k % QH_SYNC == QH_SYNC - 1) team_sync<NT>();
     }
     if constexpr (Q0 < NCH)
-        hh_range<T, NMAX, NT, HW, Q0 + 1>(S, n, lane, wave, ar, xr, sig, vr, tauk);
+        hh_range<T, NMAX, NT, HW, Q0 + 1, H>(S, n, lane, wave, ar, xr, sig, vr, tauk);
 }
 
 // Explicit Q_H = H_0 H_1 ... H_{n-3} on the AW waves that do not reduce:
@@ -1015,7 +1012,7 @@ __device__ __forceinline__ bool hh_barrier_at(const int k)
     return HW > 1 || (AW > 0 && k % QH_SYNC == QH_SYNC - 1);
 }
 
-template <typename T, int NMAX, int NT, int HW>
+template <typename T, int NMAX, int NT, int HW, typename H>
 __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, const int lane,
                                            const int wave, const bool want_q, const T sc,
                                            T (&qh)[QhShape<T, NMAX, NT>::VPL])
@@ -1057,7 +1054,6 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
     // The reduction is one dependent chain; its waves issue ahead of the
     // accumulating waves that share their SIMDs.
     if constexpr (AW > 0) __builtin_amdgcn_s_setprio(1);
-    using H = typename HhArith<T>::type;
     const int r = lane % NMAX, gl = lane / NMAX, g = wave * GW + gl;
     const bool g0 = gl == 0;
     const H hs = H(sc);  // exact power of two
@@ -1082,9 +1078,9 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
             if (r == 0) S.a[0] = T(xr);
             S.Vt[r] = T(vr);
         }
-        S.u.h.vbuf[wave * NMAX + (r % G) * CPT + r / G] = vr;
+        reinterpret_cast<H*>(S.u.h.vbuf)[wave * NMAX + (r % G) * CPT + r / G] = vr;
     }
-    hh_range<T, NMAX, NT, HW, 0>(S, n, lane, wave, ar, xr, sig, vr, tauk);
+    hh_range<T, NMAX, NT, HW, 0, H>(S, n, lane, wave, ar, xr, sig, vr, tauk);
     wave_sync();
     if (wave == 0 && g0 && n >= 2) {
         if (r == n - 2) S.a[n - 2] = T(xr);
@@ -1177,8 +1173,20 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     constexpr int AW = QH_WAVES<T, NMAX, NT>::value;
     const bool qh_wave = AW > 0 && wave >= HW && wave < HW + AW && Q_out != nullptr;
     T qh[QhShape<T, NMAX, NT>::VPL];
-    int qj = householder<T, NMAX, NT, HW>(S, n, lane, wave, Q_out != nullptr,
-                                          fexp<T>::pow2(input_shift(S)), qh);
+    // binary64 arithmetic when eigenvectors are formed; for eigenvalues alone
+    // the storage type (their error is the reduction's backward error, which
+    // no eigenvalue gap amplifies)
+    using H64 = typename HhArith<T>::type;
+    int qj;
+    if constexpr (std::is_same<H64, T>::value)
+        qj = householder<T, NMAX, NT, HW, T>(S, n, lane, wave, Q_out != nullptr,
+                                             fexp<T>::pow2(input_shift(S)), qh);
+    else if (Q_out)
+        qj = householder<T, NMAX, NT, HW, H64>(S, n, lane, wave, true,
+                                               fexp<T>::pow2(input_shift(S)), qh);
+    else
+        qj = householder<T, NMAX, NT, HW, T>(S, n, lane, wave, false,
+                                             fexp<T>::pow2(input_shift(S)), qh);
     team_sync<NT>();
     if constexpr (AW > 0) {
         // reflectors written after the last barrier of the reduction
