@@ -546,6 +546,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--only-n", type=int, default=0)
     ap.add_argument("--no-big", action="store_true", help="skip the n = 128 entry of per_n")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed batch-512 solves and their parity sample (profiler "
+                         "runs: no other launch of the same kernel)")
     ap.add_argument("--only-leg", choices=["uneven", "backward", "spectral", "serving", "leaf"],
                     default=None, help="run only this leg (for profiler passes); no JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -593,7 +596,7 @@ def main():
                          "launch_us_p90": float(np.percentile(each, 90) * 1e3)}
         print(f"[bench] n={n}: {per_n[str(n)]['eigendecomps_per_s']:.4g} matrices/s, "
               f"kernel {ev * 1e3:.1f} us", flush=True)
-        if n == 64:
+        if n == 64 and not args.main_only:
             # the same solve with one team per CU (batch = number of CUs): one
             # matrix's chain latency with nothing sharing its CU
             cus = torch.cuda.get_device_properties(0).multi_processor_count
@@ -607,7 +610,7 @@ def main():
         if n == sizes[-1]:
             main_res = (n, A_np, wall, ev, lam.cpu().numpy(), Q.cpu().numpy(), info.cpu().numpy())
 
-    if not args.only_n and not args.no_big:
+    if not args.only_n and not args.no_big and not args.main_only:
         # 64 < n <= 128: one more tearing step above the n <= 64 kernels
         nb = 128
         A_np_b, _, _ = workloads.paper_scale(nb)
@@ -635,12 +638,14 @@ def main():
     achieved = BATCH * F / (ev * 1e-3) / 1e12
     import oracle
     parity = parity_sample(oracle, A_np, lam, Q, info)
-    A = torch.from_numpy(A_np).to("cuda")
-    evals = eigenvalues_leg(bed, torch, A, A_np, oracle, args.steps, args.warmup)
-    print(f"[bench] n={n} eigenvalues only: {evals['eigendecomps_per_s']:.4g} matrices/s, "
-          f"kernel {evals['kernel_ms'] * 1e3:.1f} us", flush=True)
+    evals = None
+    if not args.main_only:
+        A = torch.from_numpy(A_np).to("cuda")
+        evals = eigenvalues_leg(bed, torch, A, A_np, oracle, args.steps, args.warmup)
+        print(f"[bench] n={n} eigenvalues only: {evals['eigendecomps_per_s']:.4g} matrices/s, "
+              f"kernel {evals['kernel_ms'] * 1e3:.1f} us", flush=True)
     uneven = backward = serving = spectral = leaves = None
-    if not args.no_extra:
+    if not args.no_extra and not args.main_only:
         leaves = leaf_leg(bed, torch, max(args.steps // 2, 10), max(args.warmup // 2, 3))
         print(f"[bench] leaf cutoff: {json.dumps(leaves)}", flush=True)
         uneven = uneven_leg(bed, torch, max(args.steps // 4, 10), max(args.warmup // 4, 3))
@@ -655,7 +660,7 @@ def main():
             serving = serving_leg(bed, torch, args.serve_requests)
             print(f"[bench] serving: saturation {serving['saturation_matrices_per_s']:.4g} "
                   "matrices/s", flush=True)
-    cpu = None if args.no_cpu else cpu_baseline(oracle, A_np, args.cpu_seconds)
+    cpu = None if (args.no_cpu or args.main_only) else cpu_baseline(oracle, A_np, args.cpu_seconds)
     line = {
         "metric": "eigendecomps/sec at n=64 fp32 batch 512 (n=32, n=48 under per_n; "
                   "p50/p99 latency under serving)",
