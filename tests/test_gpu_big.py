@@ -113,3 +113,31 @@ def test_unsupported_forms_fail_loudly():
     with pytest.raises(bed.BedError) as ei:
         bed.syevd_packed([100, 10], flat)
     assert ei.value.status == 2  # mixed batch with n > 64
+
+
+def test_graph_capture_and_replay():
+    """After a first call on a stream (which sizes its workspace), the three
+    launches of an n = 100 solve can be captured in a HIP graph; every replay,
+    with eager work in between, gives the eager result bitwise."""
+    rng = np.random.default_rng(8500)
+    A = torch.from_numpy(workloads.gaussian_sym(rng, 40, 100).astype(np.float32)).to(DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ref_l, ref_q = bed.syevd(A, stream=s)  # sizes the workspace of stream s
+    torch.cuda.synchronize()
+    lam = torch.empty_like(ref_l)
+    Q = torch.empty_like(ref_q)
+    info = torch.empty(40, dtype=torch.int32, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bed.syevd_packed([100] * 40, A.view(-1), lam=lam.view(-1), Q=Q.view(-1), info=info,
+                         stream=s)
+    for rep in range(3):
+        lam.fill_(-1.0)
+        Q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (A * 2.0).sum().item()  # eager work between replays
+        assert torch.equal(lam, ref_l) and torch.equal(Q, ref_q), f"replay {rep}"
