@@ -128,7 +128,11 @@ bed_status bed_syevd_noalloc(bed_dtype dt, int64_t batch, const int32_t *n, cons
 /* Eigenvalues only (the note forms eigenvectors only when they are required,
  * Sec. 2.3.5): Q is not produced.  The merges carry only the first and last
  * row of each node's eigenvector block -- all that the next z (Eq. (5))
- * reads -- instead of the block product, and there is no back-transform. */
+ * reads -- instead of the block product, and there is no back-transform.
+ * The Householder reduction runs in the data's own precision (bed_syevd uses
+ * binary64 arithmetic for binary32 data): an eigenvalue moves by at most the
+ * reduction's backward error, with no eigenvalue-gap factor, so the results
+ * keep bed_syevd's eigenvalue bound but are not bitwise equal to its lambda. */
 bed_status bed_syevals(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
                        void *lambda, int32_t *info, void *stream);
 
