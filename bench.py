@@ -683,6 +683,12 @@ def main():
                      "traffic": profiled_traffic(f"k_syevd_uniform_f32_n{n}_b{BATCH}"),
                      "kernel": f"k_syevd_uniform<float, {nmax_of(n)}, {threads_of(n)}>",
                      "flops_per_launch": BATCH * F, "kernel_ms": ev},
+        "latency": None if "one_team_per_cu" not in per_n.get(str(n), {}) else {
+            "one_matrix_chain_us": per_n[str(n)]["one_team_per_cu"]["kernel_ms"] * 1e3,
+            "launch_us": ev * 1e3,
+            "frac": per_n[str(n)]["one_team_per_cu"]["kernel_ms"] / ev,
+            "note": "two matrices per CU at batch 512: frac 1 would mean the second one "
+                    "costs nothing beyond one matrix's dependent chain"},
         "cpu_baseline": cpu,
         "per_n": per_n,
         "parity": parity,
