@@ -298,8 +298,8 @@ struct MrgSmem {
     float lout[BN];  // eigenvalues, ascending
     float zin[BN];
     float red[4][2];
-    uint64_t live[2], dead[2];
-    int capped, anyrot, cand;
+    uint64_t live[2], dead[2], cmask[2];
+    int capped, anyrot;
 };
 
 // One wave's 16-column tile of X = A B for the row tiles of an n x n product
@@ -359,7 +359,6 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     if (t == 0) {
         S.capped = 0;
         S.anyrot = 0;
-        S.cand = 0;
     }
     __syncthreads();
     const float rho = f_abs(md.beta);
@@ -423,9 +422,9 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     }
     __syncthreads();
     // Pairs of consecutive live elements that may pass the type-2 test (with
-    // a factor 2 of slack for the different rounding of this test): if there
-    // is one, the exact sequential scan below runs.  Rotations only follow
-    // from passing pairs, so without a candidate nothing changes.
+    // a factor 2 of slack for the different rounding of this test) mark their
+    // second element as a candidate.
+    bool cand = false;
     if (act && !defl) {
         const uint64_t l0 = S.live[0], l1 = S.live[1];
         int prev = -1;
@@ -439,36 +438,70 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
         if (prev >= 0) {
             const float zpr = S.u.m.sz[prev], dpr = S.u.m.sd[prev];
             const float rr = f_hypot(zpr, zp);
-            if (f_abs((dp - dpr) * (zp / rr) * (zpr / rr)) <= 2.f * tol) S.cand = 1;
+            cand = f_abs((dp - dpr) * (zp / rr) * (zpr / rr)) <= 2.f * tol;
         }
+    }
+    {
+        const uint64_t cm = __ballot(cand);
+        if (wave < 2 && lane == 0) S.cmask[wave] = cm;
     }
     __syncthreads();
     if (t == 0) {
-        int nr = 0;
-        if (S.cand) {
-            // consecutive live pairs (last, p) in ascending order; a passing
-            // pair is rotated, `last` deflates and p carries on
+        // The exact sequential scan over consecutive live pairs (last, p) in
+        // ascending order changes something only at a pair that passes the
+        // test.  A pair whose `last` no rotation has touched and that is not
+        // a candidate fails it, so only candidates and the successor of each
+        // rotated element are visited (as for n <= 64), each decided by the
+        // exact test.  Element masks are two 64-bit words.
+        uint64_t lv0 = S.live[0], lv1 = S.live[1];
+        uint64_t cm0 = S.cmask[0], cm1 = S.cmask[1];
+        auto lowest = [](uint64_t a0, uint64_t a1) {
+            return a0 ? __builtin_ctzll(a0) : (a1 ? 64 + __builtin_ctzll(a1) : 128);
+        };
+        int nr = 0, mod = -1;  // mod: element changed by the latest rotation
+        for (;;) {
+            int succ = 128;
+            if (mod >= 0) {  // first live element after mod
+                const uint64_t a0 = (mod < 63) ? (lv0 & ~lane_range(0, mod + 1)) : 0ull;
+                const uint64_t a1 = (mod < 63) ? lv1 : (lv1 & ~lane_range(0, mod - 63));
+                succ = lowest(a0, a1);
+            }
+            const int p = min(succ, lowest(cm0, cm1));
+            if (p >= n) break;
+            if (p < 64) cm0 &= ~(1ull << p);
+            else cm1 &= ~(1ull << (p - 64));
+            // last live element before p
             int last = -1;
-            for (int p = 0; p < n; ++p) {
-                if (S.u.m.sdefl[p]) continue;
-                if (last >= 0) {
-                    const float zl = S.u.m.sz[last], zi = S.u.m.sz[p];
-                    const float dl = S.u.m.sd[last], di = S.u.m.sd[p];
-                    const float rr = f_hypot(zl, zi);
-                    const float c = zi / rr, sn = zl / rr;
-                    if (f_abs((di - dl) * c * sn) <= tol) {
-                        S.u.m.sd[last] = dl * c * c + di * sn * sn;
-                        S.u.m.sd[p] = dl * sn * sn + di * c * c;
-                        S.u.m.sz[last] = 0.f;
-                        S.u.m.sz[p] = rr;
-                        S.u.m.sdefl[last] = 1;
-                        S.u.m.rc[last] = c;
-                        S.u.m.rs[last] = sn;
-                        S.u.m.rpart[last] = p;
-                        S.u.m.rlist[nr++] = last;
-                    }
-                }
-                last = p;
+            if (p > 64) {
+                const uint64_t b1 = lv1 & lane_range(0, p - 64);
+                last = b1 ? 64 + 63 - __builtin_clzll(b1) : (lv0 ? 63 - __builtin_clzll(lv0) : -1);
+            } else {
+                const uint64_t b0 = lv0 & lane_range(0, p);
+                last = b0 ? 63 - __builtin_clzll(b0) : -1;
+            }
+            if (last < 0) {
+                mod = -1;
+                continue;
+            }
+            const float zl = S.u.m.sz[last], zi = S.u.m.sz[p];
+            const float dl = S.u.m.sd[last], di = S.u.m.sd[p];
+            const float rr = f_hypot(zl, zi);
+            const float c = zi / rr, sn = zl / rr;
+            if (f_abs((di - dl) * c * sn) <= tol) {
+                S.u.m.sd[last] = dl * c * c + di * sn * sn;
+                S.u.m.sd[p] = dl * sn * sn + di * c * c;
+                S.u.m.sz[last] = 0.f;
+                S.u.m.sz[p] = rr;
+                S.u.m.sdefl[last] = 1;
+                S.u.m.rc[last] = c;
+                S.u.m.rs[last] = sn;
+                S.u.m.rpart[last] = p;
+                S.u.m.rlist[nr++] = last;
+                if (last < 64) lv0 &= ~(1ull << last);
+                else lv1 &= ~(1ull << (last - 64));
+                mod = p;
+            } else {
+                mod = -1;
             }
         }
         S.u.m.nrot[0] = nr;
