@@ -101,7 +101,7 @@ typedef struct bed_plan bed_plan;
  * (refused under capture, BED_ERR_CAPTURE).  A uniform binary32 batch of
  * 64 < n <= 128 runs three steps (reduction and tearing, the two halves on
  * the n <= 64 kernels, the top merge) with a workspace kept per stream
- * (about 16 (n/2)^2 + 4n + 16 bytes per matrix, grown on demand; growing it
+ * (about 8 (n/2)^2 + 12n + 24 bytes per matrix, grown on demand; growing it
  * synchronizes the stream and is refused under capture). */
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);

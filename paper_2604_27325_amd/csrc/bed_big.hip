@@ -9,10 +9,9 @@
 //                 Q_H = H_0 ... H_{n-3} formed
 //                 explicitly and staged in the Q output; T torn at s =
 //                 floor(n/2) (Eq. (3)) into T1 (s x s) and T2 ((n-s) x (n-s)),
-//                 written as dense tridiagonal matrices
-//   children      the n <= 64 kernels solve T1 and T2 (their Householder
-//                 steps are identities: a sub-column that is zero past its
-//                 first entry gives tau = 0)
+//                 written as their diagonals
+//   children      the n <= 64 solver on tridiagonal input (no reduction,
+//                 Q_H = I) solves T1 and T2
 //   k_big_merge   z = [sgn(beta) Q1(s-1, :), Q2(0, :)] (Eq. (5)), deflation,
 //                 secular roots, Loewner vectors and the merge matrix M;
 //                 Q = (Q_H diag(Q1, Q2)) M on 16x16x4 MFMA tiles, sign rule
@@ -46,7 +45,7 @@ struct Meta {
 // contiguous (child 2 of matrix b follows all children 1), so one uniform
 // launch solves both.
 struct Ws {
-    float *c1, *c2;  // dense tridiagonal children, batch x n1^2 and batch x n2^2
+    float *c1, *c2;  // children (diagonal, then off-diagonal), 2 n1 and 2 n2 values apart
     float *q1, *q2;  // their eigenvectors
     float *l1, *l2;  // their eigenvalues
     int32_t *i1, *i2;
@@ -127,8 +126,8 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     int sh = (emax == 0) ? 0 : fexp<float>::BIAS - 1 - emax;
     sh = min(max(sh, -fexp<float>::SMAX), fexp<float>::SMAX);
     if (anybad) {
-        for (int e = t; e < n1 * n1; e += BT) ws.c1[bi * n1 * n1 + e] = 0.f;
-        for (int e = t; e < n2 * n2; e += BT) ws.c2[bi * n2 * n2 + e] = 0.f;
+        for (int e = t; e < 2 * n1; e += BT) ws.c1[bi * 2 * n1 + e] = 0.f;
+        for (int e = t; e < 2 * n2; e += BT) ws.c2[bi * 2 * n2 + e] = 0.f;
         if (t == 0) ws.meta[bi] = Meta{0.f, 0, 1, 0};
         return;
     }
@@ -218,28 +217,16 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     }
     __syncthreads();
 
-    // tear (Eq. (3)) and the two children, dense
+    // tear (Eq. (3)): the two children's diagonals and off-diagonals
     {
         const float beta = S.b[s - 1];
         const float rho = f_abs(beta);
-        float *C1 = ws.c1 + bi * n1 * n1;
-        float *C2 = ws.c2 + bi * n2 * n2;
-        for (int e = t; e < n1 * n1; e += BT) {
-            const int i = e / n1, j = e % n1;
-            float v = 0.f;
-            if (i == j) v = S.a[i] - (i == s - 1 ? rho : 0.f);
-            else if (j == i + 1) v = S.b[i];
-            else if (i == j + 1) v = S.b[j];
-            C1[e] = v;
-        }
-        for (int e = t; e < n2 * n2; e += BT) {
-            const int i = e / n2, j = e % n2;
-            float v = 0.f;
-            if (i == j) v = S.a[s + i] - (i == 0 ? rho : 0.f);
-            else if (j == i + 1) v = S.b[s + i];
-            else if (i == j + 1) v = S.b[s + j];
-            C2[e] = v;
-        }
+        float *C1 = ws.c1 + bi * 2 * n1;
+        float *C2 = ws.c2 + bi * 2 * n2;
+        for (int e = t; e < 2 * n1 - 1; e += BT)
+            C1[e] = (e < n1) ? S.a[e] - (e == s - 1 ? rho : 0.f) : S.b[e - n1];
+        for (int e = t; e < 2 * n2 - 1; e += BT)
+            C2[e] = (e < n2) ? S.a[s + e] - (e == 0 ? rho : 0.f) : S.b[s + e - n2];
         if (t == 0) ws.meta[bi] = Meta{beta, sh, 0, 0};
     }
     if (!Qh) return;
@@ -631,11 +618,12 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     const int n1 = n / 2, n2 = n - n1;
     const size_t B = (size_t)batch;
     // children contiguous per kind: c1 then c2, q1 then q2, l1 then l2, i1 then i2
-    const size_t c_bytes = align_up(B * (n1 * n1 + n2 * n2) * sizeof(float));
+    const size_t c_bytes = align_up(B * 2 * (n1 + n2) * sizeof(float));
+    const size_t q_bytes = align_up(B * (n1 * n1 + n2 * n2) * sizeof(float));
     const size_t l_bytes = align_up(B * n * sizeof(float));
     const size_t i_bytes = align_up(2 * B * sizeof(int32_t));
     const size_t m_bytes = align_up(B * sizeof(Meta));
-    const size_t need = 2 * c_bytes + l_bytes + i_bytes + m_bytes;
+    const size_t need = c_bytes + q_bytes + l_bytes + i_bytes + m_bytes;
     const bool capturing = stream_capturing(s);
     char *base = nullptr;
     {
@@ -671,14 +659,14 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     }
     Ws ws;
     ws.c1 = (float *)base;
-    ws.c2 = ws.c1 + B * n1 * n1;
+    ws.c2 = ws.c1 + B * 2 * n1;
     ws.q1 = (float *)(base + c_bytes);
     ws.q2 = ws.q1 + B * n1 * n1;
-    ws.l1 = (float *)(base + 2 * c_bytes);
+    ws.l1 = (float *)(base + c_bytes + q_bytes);
     ws.l2 = ws.l1 + B * n1;
-    ws.i1 = (int32_t *)(base + 2 * c_bytes + l_bytes);
+    ws.i1 = (int32_t *)(base + c_bytes + q_bytes + l_bytes);
     ws.i2 = ws.i1 + B;
-    ws.meta = (Meta *)(base + 2 * c_bytes + l_bytes + i_bytes);
+    ws.meta = (Meta *)(base + c_bytes + q_bytes + l_bytes + i_bytes);
 
     if (Q)
         hipLaunchKernelGGL(k_big_reduce<double>, dim3((unsigned)batch), dim3(BT), 0, s,
@@ -690,14 +678,13 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     if (e != hipSuccess) return hip_fail(e, "k_big_reduce launch");
     const bed_tune dflt = default_tune();
     if (n1 == n2) {
-        e = launch_uniform(BED_F32, class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1,
-                           ws.q1, ws.i1, s);
+        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1, ws.q1,
+                       ws.i1, s);
     } else {
-        e = launch_uniform(BED_F32, class_shape(size_class(n1), dflt), ws.c1, n1, batch, ws.l1,
-                           ws.q1, ws.i1, s);
+        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, batch, ws.l1, ws.q1, ws.i1, s);
         if (e == hipSuccess)
-            e = launch_uniform(BED_F32, class_shape(size_class(n2), dflt), ws.c2, n2, batch, ws.l2,
-                               ws.q2, ws.i2, s);
+            e = launch_tri(class_shape(size_class(n2), dflt), ws.c2, n2, batch, ws.l2, ws.q2,
+                           ws.i2, s);
     }
     if (e != hipSuccess) return hip_fail(e, "child solve launch");
     hipLaunchKernelGGL(k_big_merge, dim3((unsigned)batch), dim3(BT), 0, s, n, (int64_t)batch,

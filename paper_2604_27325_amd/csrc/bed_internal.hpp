@@ -50,6 +50,11 @@ bool team_supported(bed_dtype dt, TeamShape ts);
 hipError_t launch_uniform(bed_dtype dt, TeamShape ts, const void *A, int n, int64_t batch,
                           void *lam, void *Q, int32_t *info, hipStream_t s);
 
+// Uniform batch of binary32 tridiagonal matrices (diagonal then off-diagonal,
+// 2n values apart) with eigenvectors; team shapes (32, 128) and (64, 512).
+hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, float *lam, float *Q,
+                      int32_t *info, hipStream_t s);
+
 // Work-list launch.  counter == nullptr: workgroup i handles items i, i+grid,
 // ... (static).  counter != nullptr: persistent workgroups pull items from
 // counter[0]; counter[1] counts finished workgroups and the last one resets

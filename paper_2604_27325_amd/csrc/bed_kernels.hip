@@ -26,6 +26,21 @@ k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
                             info ? info + b : nullptr, S, threadIdx.x, leaf);
 }
 
+// Uniform batch of tridiagonal matrices: matrix b is the diagonal (n values)
+// then the off-diagonal (n - 1 values) at tri + 2 n b.
+template <typename T, int NMAX, int NT>
+__global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
+k_syevd_tri(const T *__restrict__ tri, int n, int64_t batch, T *__restrict__ lam,
+            T *__restrict__ Q, int32_t *__restrict__ info, int leaf)
+{
+    __shared__ Smem<T, NMAX, NT> S;
+    const int64_t b = blockIdx.x;
+    if (b >= batch) return;
+    const int64_t n2 = (int64_t)n * n;
+    syevd_team<T, NMAX, NT, true>(tri + b * 2 * n, n, lam + b * n, Q ? Q + b * n2 : nullptr,
+                                  info ? info + b : nullptr, S, threadIdx.x, leaf);
+}
+
 // Static schedule: workgroup b solves item b.  The hardware dispatcher
 // already hands a freed compute unit the next workgroup, so a finished team's
 // slot is refilled at once.
@@ -112,6 +127,23 @@ static hipError_t uniform_t(TeamShape ts, const void *A, int n, int64_t batch, v
         return hipGetLastError();                                                           \
     }
     BED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, float *lam, float *Q,
+                      int32_t *info, hipStream_t s)
+{
+    if (batch <= 0) return hipSuccess;
+    if (!leaf_supported(ts.leaf)) return hipErrorInvalidValue;
+#define X(NM, NTT)                                                                          \
+    if (ts.nmax == NM && ts.nt == NTT) {                                                    \
+        hipLaunchKernelGGL((k_syevd_tri<float, NM, NTT>), dim3((unsigned)batch), dim3(NTT), \
+                           0, s, tri, n, batch, lam, Q, info, ts.leaf);                     \
+        return hipGetLastError();                                                           \
+    }
+    X(32, 128)
+    X(64, 512)
 #undef X
     return hipErrorInvalidValue;
 }

@@ -1091,7 +1091,10 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
     return 0;
 }
 
-template <typename T, int NMAX, int NT>
+// TRI: the input is already tridiagonal, given as its diagonal a (n values)
+// followed by its off-diagonal b (n - 1 values) at Ain; there is no reduction
+// and Q_H is the identity.
+template <typename T, int NMAX, int NT, bool TRI = false>
 __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int n,
                                            T* __restrict__ lam_out, T* __restrict__ Q_out,
                                            int* __restrict__ info_out, Smem<T, NMAX, NT>& S,
@@ -1119,7 +1122,15 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         constexpr int VW = 16 / sizeof(T);
         bool bad = false;
         T amax = T(0);
-        if (n % VW == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0) {
+        if constexpr (TRI) {
+            for (int e = t; e < 2 * n - 1; e += NT) {
+                const T v = Ain[e];
+                bad = bad || !f_finite(v);
+                amax = f_max(amax, f_abs(v));
+                if (e < n) S.a[e] = v;
+                else S.b[e - n] = v;
+            }
+        } else if (n % VW == 0 && (reinterpret_cast<uintptr_t>(Ain) & 15) == 0) {
             typedef T vec_t __attribute__((ext_vector_type(VW)));
             const vec_t* Av = reinterpret_cast<const vec_t*>(Ain);
             const int nv = n * n / VW;
@@ -1178,7 +1189,24 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     // no eigenvalue gap amplifies)
     using H64 = typename HhArith<T>::type;
     int qj;
-    if constexpr (std::is_same<H64, T>::value)
+    if constexpr (TRI) {
+        static_assert(QH_WAVES<T, NMAX, NT>::value > 0, "tridiagonal input: explicit Q_H shapes");
+        // exact power-of-two scaling of the given diagonals (the same threads
+        // wrote them); Q_H = I on the waves that would form it
+        const T sc = fexp<T>::pow2(input_shift(S));
+        for (int e = t; e < 2 * n - 1; e += NT) {
+            if (e < n) S.a[e] *= sc;
+            else S.b[e - n] *= sc;
+        }
+        if (qh_wave) {
+            constexpr int RW = QhShape<T, NMAX, NT>::RW;
+            constexpr int VPL = QhShape<T, NMAX, NT>::VPL;
+            const int row = (wave - HW) * RW + lane % RW, c0 = (lane / RW) * VPL;
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) qh[i] = (row == c0 + i) ? T(1) : T(0);
+        }
+        qj = n - 2;
+    } else if constexpr (std::is_same<H64, T>::value)
         qj = householder<T, NMAX, NT, HW, T>(S, n, lane, wave, Q_out != nullptr,
                                              fexp<T>::pow2(input_shift(S)), qh);
     else if (Q_out)
