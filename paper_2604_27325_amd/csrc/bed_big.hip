@@ -230,46 +230,140 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         if (t == 0) ws.meta[bi] = Meta{beta, sh, 0, 0};
     }
     if (!Qh) return;
-    if constexpr (!std::is_same<H, double>::value) return;  // Q_H only with binary64
+    if constexpr (std::is_same<H, double>::value) {  // Q_H only with binary64 (eigenvectors)
 
-    // Q_H = H_0 H_1 ... H_{n-3}: from the identity, H_k Q for k = n-3 .. 0.
-    // Lane (c, g) keeps column c of the rows g + 4j.
+    // Q_H = H_0 H_1 ... H_{n-3} in compact-WY blocks of 16 reflectors,
+    // H_{16b} ... H_{16b+15} = I - V_b T_b V_b^T (T_b upper triangular), applied
+    // to the identity for b = last .. 0 on 16x16x4 binary64 MFMA tiles.  The
+    // reflectors are first rounded to binary32 rows of odd stride in the same
+    // buffer (half the space; the rounding is exact to convert back), which
+    // then also holds the binary64 Gram matrices G_b = V_b^T V_b of the rounded
+    // reflectors, overwritten by the T factors (16 x 16 tiles of stride 17).
+    // T is formed with tau_j = 2 / G(j, j), so each block is exactly
+    // orthogonal for the reflectors as stored, up to binary64 rounding; only
+    // the final binary32 rounding of Q_H remains (binary32 products here would
+    // add a few 1e-6 to ||Q^T Q - I||_F at n = 128).  One wave per block forms
+    // G_b and T_b; after one barrier each wave keeps a 16-column tile of Q in
+    // accumulators through all blocks.
     {
-        const int c = r;
-        H qr[CPL];
+        using MF = Mf<double>;
+        constexpr int VLD = BN + 1;
+        constexpr int NBM = BN / 16;  // blocks at most
+        const int nb = n - 2;         // reflectors
+        const int NB = (nb + 15) / 16;
+        float *Vt = reinterpret_cast<float *>(S.V);
+        double *tf = reinterpret_cast<double *>(Vt + BN * VLD);  // G_b, then T_b
+        static_assert(sizeof(S.V) >= sizeof(float) * BN * VLD + sizeof(double) * NBM * 272,
+                      "WY buffers");
+        static_assert((sizeof(float) * BN * VLD) % sizeof(double) == 0, "WY alignment");
+        {
+            H tmp[BN * BN / BT];
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) qr[j] = (g + 4 * j == c) ? H(1) : H(0);
-        for (int k = n - 3; k >= 0; --k) {
-            const H *vk = S.V + k * BN;
-            // rows <= k: v_k is zero there (chunks of eight rows skipped)
-            H y = H(0);
-#pragma unroll
-            for (int q = 0; q < CPL / 8; ++q) {
-                if (gs + 32 * q + 28 <= k) continue;
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) y = fma(vk[g + 4 * (8 * q + jj)], qr[8 * q + jj], y);
+            for (int q = 0; q < BN * BN / BT; ++q) {
+                const int idx = t + BT * q;
+                tmp[q] = (idx / BN < nb) ? S.V[idx] : H(0);
             }
-            S.part[k & 1][g][c] = y;
             __syncthreads();
-            const int pb = k & 1;
-            const H yc = S.tau[k] * (S.part[pb][0][c] + S.part[pb][1][c] + S.part[pb][2][c] +
-                                          S.part[pb][3][c]);
 #pragma unroll
-            for (int q = 0; q < CPL / 8; ++q) {
-                if (gs + 32 * q + 28 <= k) continue;
+            for (int q = 0; q < BN * BN / BT; ++q) {
+                const int idx = t + BT * q;
+                Vt[(idx / BN) * VLD + idx % BN] = float(tmp[q]);
+            }
+            __syncthreads();
+        }
+        const int i16 = lane & 15;
+        for (int bk = wave; bk < NB; bk += BT / 64) {
+            const int k0 = 16 * bk;
+            const bool okr = k0 + i16 < nb;
+            double *tb = tf + bk * 272;
+            // G_b: one MFMA chain per row tile at or below the block (rows <= k0
+            // of its reflectors are zero), summed
+            MF::acc g = MF::zero();
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) {
-                    const int j = 8 * q + jj;
-                    qr[j] = fma(-vk[g + 4 * j], yc, qr[j]);
+            for (int rt = 0; rt < BN / 16; ++rt) {
+                if (rt < bk || 16 * rt >= n) continue;
+                MF::acc gt = MF::zero();
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const int row = 16 * rt + MF::crow(lane, s4);
+                    const double vv = okr ? double(Vt[(k0 + i16) * VLD + row]) : 0.0;
+                    gt = MF::mma(vv, vv, gt);
+                }
+                g += gt;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) tb[MF::crow(lane, v) * 17 + i16] = g[v];
+            wave_sync();
+            // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j); lane
+            // i < 16 forms row i, then (all reads of G_b done) writes it over G_b
+            if (lane < 16) {
+                double trow[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    // tau = 0 marks a skipped step (v = e_{k+1} stored, no reflection)
+                    const double tj = (k0 + j < nb && S.tau[k0 + j] != H(0))
+                                          ? 2.0 / tb[j * 17 + j] : 0.0;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], tb[kk * 17 + j], acc);
+                    trow[j] = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
+                }
+                wave_sync();
+#pragma unroll
+                for (int j = 0; j < 16; ++j) tb[lane * 17 + j] = trow[j];
+            }
+        }
+        __syncthreads();
+        const int ct = wave;  // one 16-column tile per wave (8 waves, 8 tiles)
+        if (16 * ct < n) {
+            const int c = 16 * ct + i16;
+            MF::acc qa[BN / 16];
+#pragma unroll
+            for (int rt = 0; rt < BN / 16; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) qa[rt][v] = (16 * rt + MF::crow(lane, v) == c) ? 1.0 : 0.0;
+            for (int bk = NB - 1; bk >= 0; --bk) {
+                const int k0 = 16 * bk;
+                const bool okr = k0 + i16 < nb;
+                // X = V_b^T Q (16 x 16 tile of this column block)
+                MF::acc x = MF::zero();
+#pragma unroll
+                for (int rt = 0; rt < BN / 16; ++rt) {
+                    if (rt < bk || 16 * rt >= n) continue;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int row = 16 * rt + MF::crow(lane, s4);
+                        const double va = okr ? double(Vt[(k0 + i16) * VLD + row]) : 0.0;
+                        x = MF::mma(va, qa[rt][s4], x);
+                    }
+                }
+                // Y = T_b X
+                MF::acc y = MF::zero();
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+                    y = MF::mma(tf[bk * 272 + i16 * 17 + MF::crow(lane, s4)], x[s4], y);
+                // Q -= V_b Y
+#pragma unroll
+                for (int rt = 0; rt < BN / 16; ++rt) {
+                    if (rt < bk || 16 * rt >= n) continue;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        const int kr = k0 + MF::crow(lane, s4);
+                        const double vb = (kr < nb) ? -double(Vt[kr * VLD + 16 * rt + i16]) : 0.0;
+                        qa[rt] = MF::mma(vb, y[s4], qa[rt]);
+                    }
                 }
             }
-        }
-        float *Qb = Qh + bi * n * n;
+            float *Qb = Qh + bi * n * n;
 #pragma unroll
-        for (int j = 0; j < CPL; ++j) {
-            const int row = g + 4 * j;
-            if (row < n && c < n) Qb[row * n + c] = float(qr[j]);
+            for (int rt = 0; rt < BN / 16; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rt + MF::crow(lane, v);
+                    if (row < n && c < n) Qb[row * n + c] = float(qa[rt][v]);
+                }
         }
+    }
     }
 }
 
