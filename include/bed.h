@@ -120,7 +120,8 @@ bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *
  * bed_syevd's.  The array is shared by every call on a GPU and keeps the last
  * call's list: calls that overlap in time on one GPU (different streams or
  * threads) race and give wrong results -- serialize them.  batch >
- * BED_NOALLOC_MAX_BATCH returns BED_ERR_INVALID_ARG; other errors as for
+ * BED_NOALLOC_MAX_BATCH returns BED_ERR_INVALID_ARG; orders above 64 return
+ * BED_ERR_UNSUPPORTED (their solve needs a workspace); other errors as for
  * bed_syevd.  A uniform batch needs no list and does not touch the array. */
 bed_status bed_syevd_noalloc(bed_dtype dt, int64_t batch, const int32_t *n, const void *A,
                              void *lambda, void *Q, int32_t *info, void *stream);

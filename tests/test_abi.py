@@ -64,6 +64,8 @@ def test_argument_validation_without_gpu(lib):
     n = (i32 * 2)(100, 100)
     assert lib.bed_syevd(1, ctypes.c_int64(2), n, None, None, None, None, None) == 2  # FP64 > 64
     assert lib.bed_syevd(0, ctypes.c_int64(2), n, None, None, None, None, None) == 1  # NULL A
+    # the allocation-free entry point stops at n = 64 (above, a workspace is needed)
+    assert lib.bed_syevd_noalloc(0, ctypes.c_int64(2), n, None, None, None, None, None) == 2
     n = (i32 * 2)(4, 0)
     assert lib.bed_syevd(0, ctypes.c_int64(2), n, None, None, None, None, None) == 1  # n < 1
     assert lib.bed_syevd(0, ctypes.c_int64(-1), n, None, None, None, None, None) == 1
