@@ -91,7 +91,21 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     float *St = reinterpret_cast<float *>(S.V);
     constexpr int SLD = BN + 1;
     static_assert(sizeof(S.V) + sizeof(S.x) >= sizeof(float) * BN * SLD, "load staging");
-    for (int e = t; e < n * n; e += BT) St[(e / n) * SLD + e % n] = Ab[e];
+    {
+        // lane (j, i0) = (t % BN, t / BN) reads rows i0, i0 + 4, ... at column
+        // j: every load is issued before the first LDS write
+        const int j = t & (BN - 1), i0 = t / BN;
+        float ld[BN * BN / BT];
+#pragma unroll
+        for (int q = 0; q < BN * BN / BT; ++q) {
+            const int i = i0 + (BT / BN) * q;
+            const bool in = i < n && j < n;
+            const float v = Ab[in ? i * n + j : 0];  // clamped address: no branch
+            ld[q] = in ? v : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < BN * BN / BT; ++q) St[(i0 + (BT / BN) * q) * SLD + j] = ld[q];
+    }
     __syncthreads();
     H ar[CPL];
     bool bad = false;
@@ -427,16 +441,51 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     }
     const float *Q1 = ws.q1 + bi * n1 * n1;
     const float *Q2 = ws.q2 + bi * n2 * n2;
-    // diag(Q1, Q2) into M and Q_H into W, zero outside n x n
-    for (int e = t; e < BN * LD; e += BT) {
-        const int i = e / LD, j = e % LD;
-        float v = 0.f;
-        if (i < n1 && j < n1) v = Q1[i * n1 + j];
-        else if (i >= n1 && i < n && j >= n1 && j < n) v = Q2[(i - n1) * n2 + j - n1];
-        S.M[e] = v;
-        if (Qb) S.W[e] = (i < n && j < n) ? Qb[i * n + j] : 0.f;
+    // diag(Q1, Q2) into M and Q_H into W, zero outside n x n (padding column
+    // included).  Lane (j, i0) = (t % BN, t / BN) covers rows i0, i0 + 4, ...
+    // at column j; all of its loads are issued before the first LDS write.
+    {
+        constexpr int RPL = BN * BN / BT;  // rows per lane
+        constexpr int RS = BT / BN;        // row step
+        const int j = t & (BN - 1), i0 = t / BN;
+        // raw loads from clamped addresses (Q1[0] outside both blocks, Q_H[0]
+        // outside n x n); the zeros are selected at the LDS writes
+        float mv[RPL], wv[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int i = i0 + RS * q;
+            const bool b1 = i < n1 && j < n1;
+            const bool b2 = i >= n1 && i < n && j >= n1 && j < n;
+            mv[q] = *(b1 ? Q1 + i * n1 + j : (b2 ? Q2 + (i - n1) * n2 + j - n1 : Q1));
+        }
+        if (Qb) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int i = i0 + RS * q;
+                wv[q] = Qb[(i < n && j < n) ? i * n + j : 0];
+            }
+        }
+        const float lc = (t < n) ? (t < n1 ? ws.l1[bi * n1 + t] : ws.l2[bi * n2 + t - n1]) : 0.f;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int i = i0 + RS * q;
+            const bool b1 = i < n1 && j < n1;
+            const bool b2 = i >= n1 && i < n && j >= n1 && j < n;
+            S.M[i * LD + j] = (b1 || b2) ? mv[q] : 0.f;
+        }
+        if (Qb) {
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int i = i0 + RS * q;
+                S.W[i * LD + j] = (i < n && j < n) ? wv[q] : 0.f;
+            }
+        }
+        if (t < BN) {
+            S.M[t * LD + BN] = 0.f;
+            if (Qb) S.W[t * LD + BN] = 0.f;
+        }
+        if (t < n) S.lamc[t] = lc;
     }
-    for (int e = t; e < n; e += BT) S.lamc[e] = e < n1 ? ws.l1[bi * n1 + e] : ws.l2[bi * n2 + e - n1];
     if (t == 0) {
         S.capped = 0;
         S.anyrot = 0;
