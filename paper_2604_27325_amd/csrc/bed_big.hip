@@ -56,7 +56,7 @@ struct Ws {
 template <typename H>
 struct RedSmem {
     H V[BN * BN];     // reflector v_k in row k (zero at rows <= k); load staging first
-    H x[BN];          // pivot column of the step
+    H xe[BN][2];      // pivot column as (x_r, 0) below row k + 1, (0, 1) at it: v = x rv0 + e
     H w[BN];          // w = p - (tau/2)(p^T v) v
     H part[2][4][BN]; // per column group: partial products
     H red[8];         // per wave: partial sums
@@ -75,8 +75,9 @@ struct RedSmem {
 // barrier), every lane forms the reflector (Golub-Van Loan 8.3, as for n <=
 // 64), its partial of p = tau A v and of v^T A v (second barrier), p and w
 // (third barrier), then the rank-2 update A -= v w^T + w v^T of its entries.
+// Binary32 (eigenvalues only): two teams per CU, so at most 128 VGPRs.
 template <typename H>
-__global__ void __launch_bounds__(BT)
+__global__ void __launch_bounds__(BT, sizeof(H) == 4 ? 4 : 2)
 k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restrict__ Qh, Ws ws)
 {
     __shared__ RedSmem<H> S;
@@ -90,7 +91,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     // load (coalesced, staged in LDS as binary32 over the reflector buffer)
     float *St = reinterpret_cast<float *>(S.V);
     constexpr int SLD = BN + 1;
-    static_assert(sizeof(S.V) + sizeof(S.x) >= sizeof(float) * BN * SLD, "load staging");
+    static_assert(sizeof(S.V) + sizeof(S.xe) >= sizeof(float) * BN * SLD, "load staging");
     {
         // lane (j, i0) = (t % BN, t / BN) reads rows i0, i0 + 4, ... at column
         // j: every load is issued before the first LDS write
@@ -155,20 +156,27 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     auto wlive = [&](const int k) { return rhi > k; };
     for (int k = 0; k < n - 2; ++k) {
         const int gk = k & 3, jk = k >> 2;
+        typedef H H2 __attribute__((ext_vector_type(2)));
+        H2 *xe = reinterpret_cast<H2 *>(S.xe);
         if (g == gk) {
             const H x = pick<CPL>(ar, jk);
-            S.x[r] = (r > k && r < n) ? x : H(0);
+            const bool below = r > k + 1 && r < n;
+            xe[r] = H2{below ? x : H(0), (r == k + 1) ? H(1) : H(0)};
+            if (r == k + 1) S.red[2] = x;
             if (r == k) S.a[k] = float(x);
-            const H s2 = wave_sum_all((r > k + 1 && r < n) ? x * x : H(0));
-            if (lane == 0) S.red[wave & 1] = s2;
+            const H s2 = wave_sum_all(below ? x * x : H(0));
+            if (lane == 0) S.red[__builtin_amdgcn_readfirstlane(wave & 1)] = s2;
         }
         __syncthreads();
-        const H x0 = S.x[k + 1];
+        const H x0 = S.red[2];
         const H sig = S.red[0] + S.red[1];
         const HhRefl<H> h = hh_reflector<float>(x0, sig);
-        // v = (1, x_{k+2..} rv0): x is zero at rows <= k, and past k+1 too
-        // when sig = 0, so the scaled pivot column gives v without tests
-        const H vr = (r == k + 1) ? H(1) : S.x[r] * h.rv0;
+        // v = (1, x_{k+2..} rv0) = x' rv0 + e_{k+1} with x' the pivot column
+        // zeroed at rows <= k + 1 (exact: the products are as before, and the
+        // pivot entry is exactly 1 without a per-column select); x is zero
+        // past k + 1 too when sig = 0
+        const H2 xr2 = xe[r];
+        const H vr = fma(xr2.x, h.rv0, xr2.y);
         // Dead work is skipped by wave-uniform branches: chunks of eight of a
         // lane's columns that lie at or left of column k (v is zero there and
         // the columns are never read again), and whole waves whose rows are
@@ -176,18 +184,26 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         H vc[CPL];
         H pp = H(0);
         if (wlive(k)) {
+            // independent chains against the FMA latency: four in binary64,
+            // two in binary32 (whose 128-register budget has no room for more)
+            constexpr int NC = sizeof(H) / 2;
+            H pq[NC];
+#pragma unroll
+            for (int i = 0; i < NC; ++i) pq[i] = H(0);
 #pragma unroll
             for (int q = 0; q < CPL / 8; ++q) {
                 if (gs + 32 * q + 28 <= k) continue;
 #pragma unroll
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
-                    const int c = g + 4 * j;
-                    const H xc = S.x[c];
-                    vc[j] = (c == k + 1) ? H(1) : xc * h.rv0;
-                    pp = fma(ar[j], vc[j], pp);
+                    const H2 xc = xe[g + 4 * j];
+                    vc[j] = fma(xc.x, h.rv0, xc.y);
+                    pq[jj % NC] = fma(ar[j], vc[j], pq[jj % NC]);
                 }
             }
+#pragma unroll
+            for (int i = 1; i < NC; ++i) pq[0] += pq[i];
+            pp = pq[0];
             S.part[0][g][r] = pp;
         }
         const H pv = wave_sum_all(vr * pp);  // partial of v^T A v
