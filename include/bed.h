@@ -99,10 +99,12 @@ typedef struct bed_plan bed_plan;
  * a stored persistent schedule) use a plan from an internal cache keyed by
  * (dtype, n[], stream); the first call for a new key allocates its descriptor
  * (refused under capture, BED_ERR_CAPTURE).  A uniform binary32 batch of
- * 64 < n <= 128 runs three steps (reduction and tearing, the two halves on
- * the n <= 64 kernels, the top merge) with a workspace kept per stream
- * (about 8 (n/2)^2 + 12n + 24 bytes per matrix, grown on demand; growing it
- * synchronizes the stream and is refused under capture). */
+ * 64 < n <= 128 runs in steps (reduction and tearing, the Householder
+ * product when eigenvectors are wanted, the two halves on the n <= 64
+ * kernels, the top merge) with a workspace kept per stream (about
+ * 8 (n/2)^2 + 12n + 24 bytes per matrix, plus 4n(n - 1) with eigenvectors,
+ * grown on demand; growing it synchronizes the stream and is refused under
+ * capture). */
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);
 

@@ -6,10 +6,11 @@
 //
 //   k_big_reduce  Householder tridiagonalization T = Q_H^T A Q_H with binary64
 //                 arithmetic (binary32 for eigenvalues alone, as for n <= 64);
-//                 Q_H = H_0 ... H_{n-3} formed
-//                 explicitly and staged in the Q output; T torn at s =
-//                 floor(n/2) (Eq. (3)) into T1 (s x s) and T2 ((n-s) x (n-s)),
-//                 written as their diagonals
+//                 T torn at s = floor(n/2) (Eq. (3)) into T1 (s x s) and T2
+//                 ((n-s) x (n-s)), written as their diagonals; with
+//                 eigenvectors the reflectors go to the workspace
+//   k_big_qh      Q_H = H_0 ... H_{n-3} from the reflectors in compact-WY
+//                 blocks on binary64 MFMA tiles, staged in the Q output
 //   children      the n <= 64 solver on tridiagonal input (no reduction,
 //                 Q_H = I) solves T1 and T2
 //   k_big_merge   z = [sgn(beta) Q1(s-1, :), Q2(0, :)] (Eq. (5)), deflation,
@@ -18,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <mutex>
 #include <type_traits>
 
@@ -50,18 +52,28 @@ struct Ws {
     float *l1, *l2;  // their eigenvalues
     int32_t *i1, *i2;
     Meta *meta;
+    float *v;    // with eigenvectors: reflectors v_0 .. v_{n-3} (binary32 rows of n)
+    float *tau;  // their tau (zero for a skipped step), n per matrix
 };
 
 // ------------------------------------------------------------------ reduction
+// About 66 KB, so that two teams share a CU: the load staging and the
+// buffers of the steps share the space.
 template <typename H>
 struct RedSmem {
-    H V[BN * BN];     // reflector v_k in row k (zero at rows <= k); load staging first
-    H xe[BN][2];      // pivot column as (x_r, 0) below row k + 1, (0, 1) at it: v = x rv0 + e
-    H w[BN];          // w = p - (tau/2)(p^T v) v
-    H part[2][4][BN]; // per column group: partial products
-    H red[8];         // per wave: partial sums
-    H red2[8];
-    H tau[BN];
+    static constexpr int SLD = BN + 1;  // odd stride
+    union {
+        float st[BN * SLD];  // load staging (binary32)
+        struct {
+            H xe[2][BN][2];  // pivot column as (x_r, 0) below row k + 1, (0, 1) at it
+                             // (v = x rv0 + e), by step parity: the update of step k
+                             // reads it while the next owner group writes step k + 1's
+            H w[BN];         // w = p - (tau/2)(p^T v) v
+            H part[4][BN];   // per column group: partial products
+            H red[8];        // per wave: partial sums
+            H red2[8];
+        } s;
+    } u;
     float a[BN], b[BN];
     int badw[BT / 64];
     int expw[BT / 64];
@@ -75,10 +87,11 @@ struct RedSmem {
 // barrier), every lane forms the reflector (Golub-Van Loan 8.3, as for n <=
 // 64), its partial of p = tau A v and of v^T A v (second barrier), p and w
 // (third barrier), then the rank-2 update A -= v w^T + w v^T of its entries.
-// Binary32 (eigenvalues only): two teams per CU, so at most 128 VGPRs.
+// With eigenvectors the reflectors (rounded to binary32) and their tau go to
+// the workspace for k_big_qh.  Two teams per CU: at most 128 VGPRs.
 template <typename H>
-__global__ void __launch_bounds__(BT, sizeof(H) == 4 ? 4 : 2)
-k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restrict__ Qh, Ws ws)
+__global__ void __launch_bounds__(BT, 4)
+k_big_reduce(const float *__restrict__ A, int n, int64_t batch, Ws ws)
 {
     __shared__ RedSmem<H> S;
     const int64_t bi = blockIdx.x;
@@ -89,9 +102,8 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     const float *Ab = A + bi * n * n;
 
     // load (coalesced, staged in LDS as binary32 over the reflector buffer)
-    float *St = reinterpret_cast<float *>(S.V);
-    constexpr int SLD = BN + 1;
-    static_assert(sizeof(S.V) + sizeof(S.xe) >= sizeof(float) * BN * SLD, "load staging");
+    float *St = S.u.st;
+    constexpr int SLD = RedSmem<H>::SLD;
     {
         // lane (j, i0) = (t % BN, t / BN) reads rows i0, i0 + 4, ... at column
         // j: every load is issued before the first LDS write
@@ -157,19 +169,19 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
     for (int k = 0; k < n - 2; ++k) {
         const int gk = k & 3, jk = k >> 2;
         typedef H H2 __attribute__((ext_vector_type(2)));
-        H2 *xe = reinterpret_cast<H2 *>(S.xe);
+        H2 *xe = reinterpret_cast<H2 *>(S.u.s.xe[k & 1]);
         if (g == gk) {
             const H x = pick<CPL>(ar, jk);
             const bool below = r > k + 1 && r < n;
             xe[r] = H2{below ? x : H(0), (r == k + 1) ? H(1) : H(0)};
-            if (r == k + 1) S.red[2] = x;
+            if (r == k + 1) S.u.s.red[2] = x;
             if (r == k) S.a[k] = float(x);
             const H s2 = wave_sum_all(below ? x * x : H(0));
-            if (lane == 0) S.red[__builtin_amdgcn_readfirstlane(wave & 1)] = s2;
+            if (lane == 0) S.u.s.red[__builtin_amdgcn_readfirstlane(wave & 1)] = s2;
         }
         __syncthreads();
-        const H x0 = S.red[2];
-        const H sig = S.red[0] + S.red[1];
+        const H x0 = S.u.s.red[2];
+        const H sig = S.u.s.red[0] + S.u.s.red[1];
         const HhRefl<H> h = hh_reflector<float>(x0, sig);
         // v = (1, x_{k+2..} rv0) = x' rv0 + e_{k+1} with x' the pivot column
         // zeroed at rows <= k + 1 (exact: the products are as before, and the
@@ -181,7 +193,10 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
         // lane's columns that lie at or left of column k (v is zero there and
         // the columns are never read again), and whole waves whose rows are
         // all <= k (their p and w are not used).
-        H vc[CPL];
+        // binary32 keeps v at its columns in registers (room under 128 VGPRs);
+        // binary64 forms it again in the update from the pivot pairs
+        constexpr bool HOLD = sizeof(H) == 4;
+        H vc[HOLD ? CPL : 1];
         H pp = H(0);
         if (wlive(k)) {
             // independent chains against the FMA latency: four in binary64,
@@ -197,30 +212,31 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
                     const H2 xc = xe[g + 4 * j];
-                    vc[j] = fma(xc.x, h.rv0, xc.y);
-                    pq[jj % NC] = fma(ar[j], vc[j], pq[jj % NC]);
+                    const H vj = fma(xc.x, h.rv0, xc.y);
+                    if constexpr (HOLD) vc[j] = vj;
+                    pq[jj % NC] = fma(ar[j], vj, pq[jj % NC]);
                 }
             }
 #pragma unroll
             for (int i = 1; i < NC; ++i) pq[0] += pq[i];
             pp = pq[0];
-            S.part[0][g][r] = pp;
+            S.u.s.part[g][r] = pp;
         }
         const H pv = wave_sum_all(vr * pp);  // partial of v^T A v
-        if (lane == 0) S.red2[wave] = pv;
-        if (g == 0) S.V[k * BN + r] = vr;
-        if (t == 0) {
-            S.tau[k] = h.tau;
-            S.b[k] = float(h.alpha);
+        if (lane == 0) S.u.s.red2[wave] = pv;
+        if constexpr (std::is_same<H, double>::value) {
+            if (g == 0 && r < n) ws.v[(bi * (n - 2) + k) * n + r] = float(vr);
+            if (t == 0) ws.tau[bi * n + k] = float(h.tau);
         }
+        if (t == 0) S.b[k] = float(h.alpha);
         __syncthreads();
-        const H p = h.tau * (S.part[0][0][r] + S.part[0][1][r] + S.part[0][2][r] + S.part[0][3][r]);
+        const H p = h.tau * (S.u.s.part[0][r] + S.u.s.part[1][r] + S.u.s.part[2][r] + S.u.s.part[3][r]);
         H vav = H(0);
 #pragma unroll
-        for (int w = 0; w < BT / 64; ++w) vav += S.red2[w];
+        for (int w = 0; w < BT / 64; ++w) vav += S.u.s.red2[w];
         const H ptv = h.tau * vav;  // p^T v = tau v^T A v
         const H wr = (r > k) ? p - H(0.5) * h.tau * ptv * vr : H(0);
-        if (g == 0) S.w[r] = wr;
+        if (g == 0) S.u.s.w[r] = wr;
         __syncthreads();
         if (wlive(k)) {
 #pragma unroll
@@ -230,7 +246,14 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
                     const int c = g + 4 * j;
-                    ar[j] = fma(-vr, S.w[c], fma(-wr, vc[j], ar[j]));
+                    H vj;
+                    if constexpr (HOLD) {
+                        vj = vc[j];
+                    } else {
+                        const H2 xc = xe[c];
+                        vj = fma(xc.x, h.rv0, xc.y);
+                    }
+                    ar[j] = fma(-vr, S.u.s.w[c], fma(-wr, vj, ar[j]));
                 }
             }
         }
@@ -259,142 +282,171 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, float *__restric
             C2[e] = (e < n2) ? S.a[s + e] - (e == 0 ? rho : 0.f) : S.b[s + e - n2];
         if (t == 0) ws.meta[bi] = Meta{beta, sh, 0, 0};
     }
-    if (!Qh) return;
-    if constexpr (std::is_same<H, double>::value) {  // Q_H only with binary64 (eigenvectors)
+}
 
-    // Q_H = H_0 H_1 ... H_{n-3} in compact-WY blocks of 16 reflectors,
-    // H_{16b} ... H_{16b+15} = I - V_b T_b V_b^T (T_b upper triangular), applied
-    // to the identity for b = last .. 0 on 16x16x4 binary64 MFMA tiles.  The
-    // reflectors are first rounded to binary32 rows of odd stride in the same
-    // buffer (half the space; the rounding is exact to convert back), which
-    // then also holds the binary64 Gram matrices G_b = V_b^T V_b of the rounded
-    // reflectors, overwritten by the T factors (16 x 16 tiles of stride 17).
-    // T is formed with tau_j = 2 / G(j, j), so each block is exactly
-    // orthogonal for the reflectors as stored, up to binary64 rounding; only
-    // the final binary32 rounding of Q_H remains (binary32 products here would
-    // add a few 1e-6 to ||Q^T Q - I||_F at n = 128).  One wave per block forms
-    // G_b and T_b; after one barrier each wave keeps a 16-column tile of Q in
-    // accumulators through all blocks.
+// ------------------------------------------------------------------ Q_H
+// Q_H = H_0 H_1 ... H_{n-3} in compact-WY blocks of 16 reflectors,
+// H_{16b} ... H_{16b+15} = I - V_b T_b V_b^T (T_b upper triangular), applied to
+// the identity for b = last .. 0 on 16x16x4 binary64 MFMA tiles.  The
+// reflectors come rounded to binary32 (exact to convert back) and are staged
+// in LDS at odd stride; the binary64 Gram matrices G_b = V_b^T V_b of the
+// rounded reflectors and then the T factors sit in packed upper triangles
+// (element (i, j) at j (j + 1) / 2 + i).  T is formed with tau_j = 2 / G(j, j),
+// so each block is exactly orthogonal for the reflectors as stored, up to
+// binary64 rounding; only the final binary32 rounding of Q_H remains
+// (binary32 products here would add a few 1e-6 to ||Q^T Q - I||_F at n = 128).
+// One wave per block forms G_b and T_b; after one barrier each wave keeps a
+// 16-column tile of Q in accumulators through all blocks.
+struct QhSmem {
+    static constexpr int VLD = BN + 1;
+    static constexpr int TP = 136;  // packed 16 x 16 upper triangle
+    float V[BN * VLD];
+    double tf[(BN / 16) * TP];  // G_b, then T_b
+};
+
+__global__ void __launch_bounds__(BT, 4)  // two teams per CU
+k_big_qh(int n, int64_t batch, float *__restrict__ Qh, Ws ws)
+{
+    __shared__ QhSmem S;
+    using MF = Mf<double>;
+    constexpr int VLD = QhSmem::VLD;
+    constexpr int TP = QhSmem::TP;
+    const int64_t bi = blockIdx.x;
+    if (bi >= batch) return;
+    if (ws.meta[bi].bad) return;  // the merge writes NaN
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nb = n - 2;  // reflectors
+    const int NB = (nb + 15) / 16;
     {
-        using MF = Mf<double>;
-        constexpr int VLD = BN + 1;
-        constexpr int NBM = BN / 16;  // blocks at most
-        const int nb = n - 2;         // reflectors
-        const int NB = (nb + 15) / 16;
-        float *Vt = reinterpret_cast<float *>(S.V);
-        double *tf = reinterpret_cast<double *>(Vt + BN * VLD);  // G_b, then T_b
-        static_assert(sizeof(S.V) >= sizeof(float) * BN * VLD + sizeof(double) * NBM * 272,
-                      "WY buffers");
-        static_assert((sizeof(float) * BN * VLD) % sizeof(double) == 0, "WY alignment");
-        {
-            H tmp[BN * BN / BT];
+        // lane (j, i0) = (t % BN, t / BN) stages rows i0, i0 + 4, ... at column
+        // j (zero outside the nb x n reflector block), loads first
+        constexpr int RPL = BN * BN / BT, RS = BT / BN;
+        const int j = t & (BN - 1), i0 = t / BN;
+        const float *Vb = ws.v + bi * nb * n;
+        float ld[RPL];
 #pragma unroll
-            for (int q = 0; q < BN * BN / BT; ++q) {
-                const int idx = t + BT * q;
-                tmp[q] = (idx / BN < nb) ? S.V[idx] : H(0);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < BN * BN / BT; ++q) {
-                const int idx = t + BT * q;
-                Vt[(idx / BN) * VLD + idx % BN] = float(tmp[q]);
-            }
-            __syncthreads();
+        for (int q = 0; q < RPL; ++q) {
+            const int i = i0 + RS * q;
+            ld[q] = Vb[(i < nb && j < n) ? i * n + j : 0];
         }
-        const int i16 = lane & 15;
-        for (int bk = wave; bk < NB; bk += BT / 64) {
-            const int k0 = 16 * bk;
-            const bool okr = k0 + i16 < nb;
-            double *tb = tf + bk * 272;
-            // G_b: one MFMA chain per row tile at or below the block (rows <= k0
-            // of its reflectors are zero), summed
-            MF::acc g = MF::zero();
 #pragma unroll
-            for (int rt = 0; rt < BN / 16; ++rt) {
-                if (rt < bk || 16 * rt >= n) continue;
-                MF::acc gt = MF::zero();
+        for (int q = 0; q < RPL; ++q) {
+            const int i = i0 + RS * q;
+            S.V[i * VLD + j] = (i < nb && j < n) ? ld[q] : 0.f;
+        }
+    }
+    __syncthreads();
+    auto tix = [](int i, int j) { return ((j * (j + 1)) >> 1) + i; };  // i <= j
+    const int i16 = lane & 15;
+    for (int bk = wave; bk < NB; bk += BT / 64) {
+        const int k0 = 16 * bk;
+        double *tb = S.tf + bk * TP;
+        // G_b: one MFMA chain per row tile at or below the block (rows <= k0 of
+        // its reflectors are zero), summed
+        MF::acc g = MF::zero();
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) {
-                    const int row = 16 * rt + MF::crow(lane, s4);
-                    const double vv = okr ? double(Vt[(k0 + i16) * VLD + row]) : 0.0;
-                    gt = MF::mma(vv, vv, gt);
-                }
-                g += gt;
+        for (int rt = 0; rt < BN / 16; ++rt) {
+            if (rt < bk || 16 * rt >= n) continue;
+            MF::acc gt = MF::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double vv = S.V[(k0 + i16) * VLD + 16 * rt + MF::crow(lane, s4)];
+                gt = MF::mma(vv, vv, gt);
             }
+            g += gt;
+        }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) tb[MF::crow(lane, v) * 17 + i16] = g[v];
+        for (int v = 0; v < 4; ++v) {
+            const int gr = MF::crow(lane, v);
+            if (gr <= i16) tb[tix(gr, i16)] = g[v];
+        }
+        wave_sync();
+        // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j); lane i <
+        // 16 forms row i, then (all reads of G_b done) writes it over G_b
+        // tau_j = 2 / G(j, j) on lane j (zero marks a skipped step: v = e_{k+1}
+        // stored, no reflection), then broadcast
+        double tl = 0.0;
+        if (lane < 16 && k0 + lane < nb && ws.tau[bi * n + k0 + lane] != 0.f)
+            tl = 2.0 / tb[tix(lane, lane)];
+        if (lane < 16) {
+            double trow[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const double tj = __shfl(tl, j);
+                // column j's loads are made to wait for T(i, j - 1) through an
+                // empty asm (hoisting all 120 would exhaust the registers)
+                int cb = tix(0, j);
+                if (j > 0) asm volatile("" : "+v"(cb) : "v"(trow[j - 1]));
+                double acc = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], tb[cb + kk], acc);
+                trow[j] = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
+            }
             wave_sync();
-            // T_b: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j); lane
-            // i < 16 forms row i, then (all reads of G_b done) writes it over G_b
-            if (lane < 16) {
-                double trow[16];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    // tau = 0 marks a skipped step (v = e_{k+1} stored, no reflection)
-                    const double tj = (k0 + j < nb && S.tau[k0 + j] != H(0))
-                                          ? 2.0 / tb[j * 17 + j] : 0.0;
-                    double acc = 0.0;
-#pragma unroll
-                    for (int kk = 0; kk < j; ++kk) acc = fma(trow[kk], tb[kk * 17 + j], acc);
-                    trow[j] = (lane < j) ? -tj * acc : (lane == j ? tj : 0.0);
-                }
-                wave_sync();
-#pragma unroll
-                for (int j = 0; j < 16; ++j) tb[lane * 17 + j] = trow[j];
-            }
-        }
-        __syncthreads();
-        const int ct = wave;  // one 16-column tile per wave (8 waves, 8 tiles)
-        if (16 * ct < n) {
-            const int c = 16 * ct + i16;
-            MF::acc qa[BN / 16];
-#pragma unroll
-            for (int rt = 0; rt < BN / 16; ++rt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) qa[rt][v] = (16 * rt + MF::crow(lane, v) == c) ? 1.0 : 0.0;
-            for (int bk = NB - 1; bk >= 0; --bk) {
-                const int k0 = 16 * bk;
-                const bool okr = k0 + i16 < nb;
-                // X = V_b^T Q (16 x 16 tile of this column block)
-                MF::acc x = MF::zero();
-#pragma unroll
-                for (int rt = 0; rt < BN / 16; ++rt) {
-                    if (rt < bk || 16 * rt >= n) continue;
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) {
-                        const int row = 16 * rt + MF::crow(lane, s4);
-                        const double va = okr ? double(Vt[(k0 + i16) * VLD + row]) : 0.0;
-                        x = MF::mma(va, qa[rt][s4], x);
-                    }
-                }
-                // Y = T_b X
-                MF::acc y = MF::zero();
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
-                    y = MF::mma(tf[bk * 272 + i16 * 17 + MF::crow(lane, s4)], x[s4], y);
-                // Q -= V_b Y
-#pragma unroll
-                for (int rt = 0; rt < BN / 16; ++rt) {
-                    if (rt < bk || 16 * rt >= n) continue;
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) {
-                        const int kr = k0 + MF::crow(lane, s4);
-                        const double vb = (kr < nb) ? -double(Vt[kr * VLD + 16 * rt + i16]) : 0.0;
-                        qa[rt] = MF::mma(vb, y[s4], qa[rt]);
-                    }
-                }
-            }
-            float *Qb = Qh + bi * n * n;
-#pragma unroll
-            for (int rt = 0; rt < BN / 16; ++rt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = 16 * rt + MF::crow(lane, v);
-                    if (row < n && c < n) Qb[row * n + c] = float(qa[rt][v]);
-                }
+            for (int j = 0; j < 16; ++j)
+                if (lane <= j) tb[tix(lane, j)] = trow[j];
         }
     }
+    __syncthreads();
+    // One 16-column tile per wave.  Block b leaves a column c < 16 b of the
+    // identity unchanged (v_k is zero at rows <= k), so tile ct takes only
+    // the blocks b <= ct; waves w and w + 4 (one SIMD when waves are placed
+    // round robin) take tiles w and 7 - w, which balances the work.
+    const int ct = (wave < 4) ? wave : 11 - wave;
+    if (16 * ct >= n) return;
+    const int c = 16 * ct + i16;
+    MF::acc qa[BN / 16];
+#pragma unroll
+    for (int rt = 0; rt < BN / 16; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) qa[rt][v] = (16 * rt + MF::crow(lane, v) == c) ? 1.0 : 0.0;
+    for (int bk = min(NB - 1, ct); bk >= 0; --bk) {
+        const int k0 = 16 * bk;
+        // X = V_b^T Q (16 x 16 tile of this column block); staged rows past the
+        // last reflector are zero
+        MF::acc xp[2] = {MF::zero(), MF::zero()};  // two chains (MFMA latency)
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt) {
+            if (rt < bk || 16 * rt >= n) continue;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double va = S.V[(k0 + i16) * VLD + 16 * rt + MF::crow(lane, s4)];
+                xp[rt & 1] = MF::mma(va, qa[rt][s4], xp[rt & 1]);
+            }
+        }
+        MF::acc x;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = xp[0][v] + xp[1][v];
+        // Y = T_b X
+        MF::acc y = MF::zero();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = MF::crow(lane, s4);
+            const double ta = (kk >= i16) ? S.tf[bk * TP + tix(i16, kk)] : 0.0;
+            y = MF::mma(ta, x[s4], y);
+        }
+        // Q -= V_b Y (its operand loads are not hoisted above X: the register
+        // budget holds one product's operands at a time)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rt = 0; rt < BN / 16; ++rt) {
+            if (rt < bk || 16 * rt >= n) continue;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double vb = -double(S.V[(k0 + MF::crow(lane, s4)) * VLD + 16 * rt + i16]);
+                qa[rt] = MF::mma(vb, y[s4], qa[rt]);
+            }
+        }
     }
+    float *Qb = Qh + bi * n * n;
+#pragma unroll
+    for (int rt = 0; rt < BN / 16; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * rt + MF::crow(lane, v);
+            if (row < n && c < n) Qb[row * n + c] = float(qa[rt][v]);
+        }
 }
 
 // ------------------------------------------------------------------ top merge
@@ -782,7 +834,9 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     const size_t l_bytes = align_up(B * n * sizeof(float));
     const size_t i_bytes = align_up(2 * B * sizeof(int32_t));
     const size_t m_bytes = align_up(B * sizeof(Meta));
-    const size_t need = c_bytes + q_bytes + l_bytes + i_bytes + m_bytes;
+    const size_t v_bytes = Q ? align_up(B * (n - 2) * n * sizeof(float)) : 0;
+    const size_t t_bytes = Q ? align_up(B * n * sizeof(float)) : 0;
+    const size_t need = c_bytes + q_bytes + l_bytes + i_bytes + m_bytes + v_bytes + t_bytes;
     const bool capturing = stream_capturing(s);
     char *base = nullptr;
     {
@@ -826,15 +880,24 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     ws.i1 = (int32_t *)(base + c_bytes + q_bytes + l_bytes);
     ws.i2 = ws.i1 + B;
     ws.meta = (Meta *)(base + c_bytes + q_bytes + l_bytes + i_bytes);
+    ws.v = Q ? (float *)(base + c_bytes + q_bytes + l_bytes + i_bytes + m_bytes) : nullptr;
+    ws.tau = Q ? (float *)(base + c_bytes + q_bytes + l_bytes + i_bytes + m_bytes + v_bytes)
+               : nullptr;
 
     if (Q)
         hipLaunchKernelGGL(k_big_reduce<double>, dim3((unsigned)batch), dim3(BT), 0, s,
-                           (const float *)A, n, (int64_t)batch, (float *)Q, ws);
+                           (const float *)A, n, (int64_t)batch, ws);
     else
         hipLaunchKernelGGL(k_big_reduce<float>, dim3((unsigned)batch), dim3(BT), 0, s,
-                           (const float *)A, n, (int64_t)batch, (float *)nullptr, ws);
+                           (const float *)A, n, (int64_t)batch, ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "k_big_reduce launch");
+    if (Q) {
+        hipLaunchKernelGGL(k_big_qh, dim3((unsigned)batch), dim3(BT), 0, s, n, (int64_t)batch,
+                           (float *)Q, ws);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "k_big_qh launch");
+    }
     const bed_tune dflt = default_tune();
     if (n1 == n2) {
         e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1, ws.q1,
