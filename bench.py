@@ -681,7 +681,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
                      "traffic": profiled_traffic(f"k_syevd_uniform_f32_n{n}_b{BATCH}"),
-                     "kernel": f"k_syevd_uniform<float, {nmax_of(n)}, {threads_of(n)}>",
+                     "kernel": (f"k_syevd_uniform<float, {nmax_of(n)}, {threads_of(n)}>" if n <= 64
+                                else "k_big_reduce, k_big_qh, k_syevd_tri, k_big_merge (one solve)"),
                      "flops_per_launch": BATCH * F, "kernel_ms": ev},
         "latency": None if "one_team_per_cu" not in per_n.get(str(n), {}) else {
             "one_matrix_chain_us": per_n[str(n)]["one_team_per_cu"]["kernel_ms"] * 1e3,
