@@ -626,7 +626,7 @@ def main():
                           "launch_us_median": float(np.median(each_b) * 1e3),
                           "launch_us_p10": float(np.percentile(each_b, 10) * 1e3),
                           "launch_us_p90": float(np.percentile(each_b, 90) * 1e3),
-                          "kernels": "reduce + tear, halves on the n <= 64 kernels, top merge",
+                          "kernels": "reduce + tear, Householder product, halves on the n <= 64 kernels, top merge",
                           "parity": parity_sample(_orc, A_np_b, lam_b.cpu().numpy(),
                                                   Q_b.cpu().numpy(), info_b.cpu().numpy())}
         print(f"[bench] n={nb}: {per_n[str(nb)]['eigendecomps_per_s']:.4g} matrices/s, "

@@ -116,9 +116,10 @@ def test_unsupported_forms_fail_loudly():
 
 
 def test_graph_capture_and_replay():
-    """After a first call on a stream (which sizes its workspace), the three
-    launches of an n = 100 solve can be captured in a HIP graph; every replay,
-    with eager work in between, gives the eager result bitwise."""
+    """After a first call on a stream (which sizes its workspace), the
+    launches of an n = 100 solve (reduction, Householder product, halves, top
+    merge) can be captured in a HIP graph; every replay, with eager work in
+    between, gives the eager result bitwise."""
     rng = np.random.default_rng(8500)
     A = torch.from_numpy(workloads.gaussian_sym(rng, 40, 100).astype(np.float32)).to(DEV)
     s = torch.cuda.Stream()
