@@ -104,6 +104,23 @@ def test_nonfinite_input_reports_info_minus_one():
     assert torch.isfinite(lam[0]).all() and torch.isfinite(Q[2]).all()
 
 
+def test_nonfinite_input_eigenvalues_only():
+    """The binary32 reduction path (eigenvalues only) flags a NaN matrix the
+    same way and leaves its neighbours intact."""
+    rng = np.random.default_rng(8401)
+    A_np = workloads.gaussian_sym(rng, 4, 128).astype(np.float32)
+    A_np[2, 3, 120] = np.inf
+    A = torch.from_numpy(A_np).to(DEV)
+    lam, _, info = bed.syevd_packed([128] * 4, A.view(-1), want_vectors=False)
+    lam = lam.view(4, 128)
+    info = info.cpu().numpy()
+    assert list(info) == [0, 0, -1, 0]
+    assert torch.isnan(lam[2]).all()
+    lam_o, _, _ = oracle.syevd(A_np[[0, 1, 3]].astype(np.float64))
+    err = np.abs(lam[[0, 1, 3]].cpu().numpy() - lam_o).max() / np.abs(lam_o).max()
+    assert err < 1e-5, err
+
+
 def test_unsupported_forms_fail_loudly():
     A = torch.zeros(2, 100, 100, dtype=torch.float64, device=DEV)
     with pytest.raises(bed.BedError) as ei:
@@ -142,3 +159,28 @@ def test_graph_capture_and_replay():
         torch.cuda.synchronize()
         _ = (A * 2.0).sum().item()  # eager work between replays
         assert torch.equal(lam, ref_l) and torch.equal(Q, ref_q), f"replay {rep}"
+
+
+def test_graph_capture_eigenvalues_only():
+    """The eigenvalues-only chain (binary32 reduction, halves, top merge) of
+    an odd order captured in a HIP graph: every replay equals the eager
+    result bitwise."""
+    rng = np.random.default_rng(8501)
+    A = torch.from_numpy(workloads.gaussian_sym(rng, 24, 101).astype(np.float32)).to(DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ref, _, _ = bed.syevd_packed([101] * 24, A.view(-1), want_vectors=False, stream=s)
+    torch.cuda.synchronize()
+    lam = torch.empty_like(ref)
+    info = torch.empty(24, dtype=torch.int32, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bed.syevd_packed([101] * 24, A.view(-1), lam=lam, info=info, want_vectors=False, stream=s)
+    for rep in range(3):
+        lam.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = (A * 2.0).sum().item()
+        assert torch.equal(lam, ref), f"replay {rep}"
