@@ -452,42 +452,27 @@ k_big_qh(int n, int64_t batch, float *__restrict__ Qh, Ws ws)
 // ------------------------------------------------------------------ top merge
 struct MrgSmem {
     static constexpr int LD = BN + 1;  // odd stride; column BN is the padding column of M
-    float W[BN * LD];  // Q_H staged, then Q_H diag(Q1, Q2)
-    float M[BN * LD];  // diag(Q1, Q2) staged, then the merge matrix
+    // rows 0 and 1 first hold the children's eigenvalues and z; then the
+    // merge matrix M; then E = diag(Q1, Q2) M
+    float M[BN * LD];
+    // merge state; after the secular solve, the sign candidates of Q
     struct {
         MergeArrays<float, BN> m;
     } u;
-    float lamc[BN];  // children's eigenvalues, D1 then D2
     float lout[BN];  // eigenvalues, ascending
-    float zin[BN];
     float red[4][2];
     uint64_t live[2], dead[2], cmask[2];
     int capped, anyrot;
 };
 
-// One wave's 16-column tile of X = A B for the row tiles of an n x n product
-// held in LDS (zero padding up to the tile sizes), in accumulators.
-__device__ __forceinline__ void tile_product(const float *__restrict__ Am,
-                                             const float *__restrict__ Bm, const int n,
-                                             const int ct, const int lane, f32x4 (&acc)[BN / 16])
-{
-    using MF = Mf<float>;
-    constexpr int LD = MrgSmem::LD;
-    const int i16 = lane & 15, kk = lane >> 4;
-    const int c = 16 * ct + i16;
-    const int ks = (n + 3) >> 2;
-#pragma unroll
-    for (int rt = 0; rt < BN / 16; ++rt) acc[rt] = MF::zero();
-    for (int s4 = 0; s4 < ks; ++s4) {
-        const int k = 4 * s4 + kk;
-        const float bv = Bm[k * LD + c];
-#pragma unroll
-        for (int rt = 0; rt < BN / 16; ++rt)
-            if (16 * rt < n) acc[rt] = MF::mma(Am[(16 * rt + i16) * LD + k], bv, acc[rt]);
-    }
-}
+// Per wave and column: the entry of largest magnitude of the wave's rows of Q
+// (lowest row on ties), signed.
+struct SignCand {
+    float val;
+    int row;
+};
 
-__global__ void __launch_bounds__(BT)
+__global__ void __launch_bounds__(BT, 4)  // two teams per CU
 k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q,
             int32_t *__restrict__ info, Ws ws)
 {
@@ -509,81 +494,31 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     }
     const float *Q1 = ws.q1 + bi * n1 * n1;
     const float *Q2 = ws.q2 + bi * n2 * n2;
-    // diag(Q1, Q2) into M and Q_H into W, zero outside n x n (padding column
-    // included).  Lane (j, i0) = (t % BN, t / BN) covers rows i0, i0 + 4, ...
-    // at column j; all of its loads are issued before the first LDS write.
-    {
-        constexpr int RPL = BN * BN / BT;  // rows per lane
-        constexpr int RS = BT / BN;        // row step
-        const int j = t & (BN - 1), i0 = t / BN;
-        // raw loads from clamped addresses (Q1[0] outside both blocks, Q_H[0]
-        // outside n x n); the zeros are selected at the LDS writes
-        float mv[RPL], wv[RPL];
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int i = i0 + RS * q;
-            const bool b1 = i < n1 && j < n1;
-            const bool b2 = i >= n1 && i < n && j >= n1 && j < n;
-            mv[q] = *(b1 ? Q1 + i * n1 + j : (b2 ? Q2 + (i - n1) * n2 + j - n1 : Q1));
-        }
-        if (Qb) {
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int i = i0 + RS * q;
-                wv[q] = Qb[(i < n && j < n) ? i * n + j : 0];
-            }
-        }
-        const float lc = (t < n) ? (t < n1 ? ws.l1[bi * n1 + t] : ws.l2[bi * n2 + t - n1]) : 0.f;
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int i = i0 + RS * q;
-            const bool b1 = i < n1 && j < n1;
-            const bool b2 = i >= n1 && i < n && j >= n1 && j < n;
-            S.M[i * LD + j] = (b1 || b2) ? mv[q] : 0.f;
-        }
-        if (Qb) {
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-                const int i = i0 + RS * q;
-                S.W[i * LD + j] = (i < n && j < n) ? wv[q] : 0.f;
-            }
-        }
-        if (t < BN) {
-            S.M[t * LD + BN] = 0.f;
-            if (Qb) S.W[t * LD + BN] = 0.f;
-        }
-        if (t < n) S.lamc[t] = lc;
+    const float rho = f_abs(md.beta);
+    const float sgm = (md.beta < 0.f) ? -1.f : 1.f;
+    // the children's eigenvalues, and z (Eq. (5)): sgn(beta) times the last
+    // row of Q1 over the first row of Q2, into rows 0 and 1 of M
+    float *lamc = S.M, *zin = S.M + LD;
+    if (t < n) {
+        lamc[t] = (t < n1) ? ws.l1[bi * n1 + t] : ws.l2[bi * n2 + t - n1];
+        zin[t] = (t < n1) ? sgm * Q1[(n1 - 1) * n1 + t] : Q2[t - n1];
     }
     if (t == 0) {
         S.capped = 0;
         S.anyrot = 0;
     }
     __syncthreads();
-    const float rho = f_abs(md.beta);
-    const float sgm = (md.beta < 0.f) ? -1.f : 1.f;
-    // z (Eq. (5)): sgn(beta) times the last row of Q1 over the first row of Q2
-    if (t < n) S.zin[t] = (t < n1) ? sgm * S.M[(n1 - 1) * LD + t] : S.M[n1 * LD + t];
-    f32x4 acc[BN / 16];
-    if (Qb && 16 * wave < n) tile_product(S.W, S.M, n, wave, lane, acc);
-    __syncthreads();
-    if (Qb && 16 * wave < n) {
-        const int c = 16 * wave + (lane & 15);
-#pragma unroll
-        for (int rt = 0; rt < BN / 16; ++rt)
-            if (16 * rt < n)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) S.W[(16 * rt + MF::crow(lane, v)) * LD + c] = acc[rt][v];
-    }
     // stable merge of the two ascending child lists
     if (t < n) {
-        const float de = S.lamc[t], ze = S.zin[t];
+        const float de = lamc[t], ze = zin[t];
         const bool left = t < n1;
         const int pos = (left ? t : t - n1) +
-                        count_below(S.lamc + (left ? n1 : 0), left ? n2 : n1, de, !left);
+                        count_below(lamc + (left ? n1 : 0), left ? n2 : n1, de, !left);
         S.u.m.sd[pos] = de;
         S.u.m.sz[pos] = ze;
         S.u.m.sperm[pos] = t;
     }
+    __syncthreads();
     for (int e = t; e < BN * LD; e += BT) S.M[e] = 0.f;  // the merge matrix, zero padded
     __syncthreads();
 
@@ -754,49 +689,138 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     // ---- secular roots, Loewner vectors, merge matrix (one node, depth 0) --
     roots_vectors<float, BN, BT, BN / (BT / BN)>(S, n, 0, t, S.lout, BN / 2);
 
-    // ---- Q = W M with the sign rule, eigenvalues, info ---------------------
-    if (Qb && 16 * wave < n) {
-        tile_product(S.W, S.M, n, wave, lane, acc);
-        const int c = 16 * wave + (lane & 15);
-        float best = -1.f, bval = 0.f;
-        int brow = 1 << 20;
+    // ---- Q = Q_H (diag(Q1, Q2) M) with the sign rule ------------------------
+    // Wave w takes row tile w of both products on 16x16x4 MFMA tiles, its A
+    // rows (diag(Q1, Q2), then Q_H) loaded from HBM into registers, B from
+    // LDS; E = diag(Q1, Q2) M replaces M.  Each wave then leaves, per column,
+    // its entry of largest magnitude (lowest row on ties), a barrier later
+    // the column's sign is known, and each wave stores its rows.
+    if (Qb) {
+        using MF = Mf<float>;
+        constexpr int KS = BN / 4;  // k steps
+        const int i16 = lane & 15, kk = lane >> 4;
+        const int r = 16 * wave + i16;  // this lane's A row
+        const bool rows = 16 * wave < n;
+        f32x4 acc[BN / 16];
+        float a[KS];
+        if (rows) {
+            // loads from clamped addresses (Q1[0] outside both blocks), the
+            // zeros selected afterwards
 #pragma unroll
-        for (int rt = 0; rt < BN / 16; ++rt) {
-            if (16 * rt >= n) continue;
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int k = 4 * s4 + kk;
+                const bool b1 = r < n1 && k < n1;
+                const bool b2 = r >= n1 && r < n && k >= n1 && k < n;
+                a[s4] = *(b1 ? Q1 + r * n1 + k : (b2 ? Q2 + (r - n1) * n2 + (k - n1) : Q1));
+            }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rt + MF::crow(lane, v);
-                const float av = f_abs(acc[rt][v]);
-                const bool take = row < n && (av > best || (av == best && row < brow));
-                best = take ? av : best;
-                brow = take ? row : brow;
-                bval = take ? acc[rt][v] : bval;
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int k = 4 * s4 + kk;
+                const bool b1 = r < n1 && k < n1;
+                const bool b2 = r >= n1 && r < n && k >= n1 && k < n;
+                a[s4] = (b1 || b2) ? a[s4] : 0.f;
+            }
+#pragma unroll
+            for (int ct = 0; ct < BN / 16; ++ct) acc[ct] = MF::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const float *mrow = S.M + (4 * s4 + kk) * LD + i16;
+#pragma unroll
+                for (int ct = 0; ct < BN / 16; ++ct) acc[ct] = MF::mma(a[s4], mrow[16 * ct], acc[ct]);
             }
         }
-        {
-            const float ob = xmove<16>(best, lane);
-            const int orow = xmove<16>(brow, lane);
-            const float oval = xmove<16>(bval, lane);
-            const bool take = ob > best || (ob == best && orow < brow);
-            best = take ? ob : best;
-            brow = take ? orow : brow;
-            bval = take ? oval : bval;
-        }
-        {
-            const float ob = xmove<32>(best, lane);
-            const int orow = xmove<32>(brow, lane);
-            const float oval = xmove<32>(bval, lane);
-            const bool take = ob > best || (ob == best && orow < brow);
-            bval = take ? oval : bval;
-        }
-        const float sgn = (bval < 0.f) ? -1.f : 1.f;
+        __syncthreads();  // every read of M is done
+        if (rows) {
 #pragma unroll
-        for (int rt = 0; rt < BN / 16; ++rt) {
-            if (16 * rt >= n) continue;
+            for (int ct = 0; ct < BN / 16; ++ct)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * rt + MF::crow(lane, v);
-                if (row < n && c < n) Qb[row * n + c] = sgn * acc[rt][v];
+                for (int v = 0; v < 4; ++v)
+                    S.M[(16 * wave + MF::crow(lane, v)) * LD + 16 * ct + i16] = acc[ct][v];
+            // Q_H rows of this tile (held in the Q output; only this wave
+            // reads or writes them)
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int k = 4 * s4 + kk;
+                a[s4] = Qb[(r < n && k < n) ? r * n + k : 0];
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const int k = 4 * s4 + kk;
+                a[s4] = (r < n && k < n) ? a[s4] : 0.f;
+            }
+        }
+        __syncthreads();  // E complete
+        SignCand *cand = reinterpret_cast<SignCand *>(&S.u);  // [wave][column]
+        float *csign = reinterpret_cast<float *>(cand + (BT / 64) * BN);
+        static_assert(sizeof(S.u) >= sizeof(SignCand) * (BT / 64) * BN + sizeof(float) * BN,
+                      "sign candidates");
+        if (rows) {
+#pragma unroll
+            for (int ct = 0; ct < BN / 16; ++ct) acc[ct] = MF::zero();
+#pragma unroll
+            for (int s4 = 0; s4 < KS; ++s4) {
+                const float *erow = S.M + (4 * s4 + kk) * LD + i16;
+#pragma unroll
+                for (int ct = 0; ct < BN / 16; ++ct) acc[ct] = MF::mma(a[s4], erow[16 * ct], acc[ct]);
+            }
+#pragma unroll
+            for (int ct = 0; ct < BN / 16; ++ct) {
+                float best = -1.f, bval = 0.f;
+                int brow = 1 << 20;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * wave + MF::crow(lane, v);
+                    const float av = f_abs(acc[ct][v]);
+                    const bool take = row < n && (av > best || (av == best && row < brow));
+                    best = take ? av : best;
+                    brow = take ? row : brow;
+                    bval = take ? acc[ct][v] : bval;
+                }
+                {
+                    const float ob = xmove<16>(best, lane);
+                    const int orow = xmove<16>(brow, lane);
+                    const float oval = xmove<16>(bval, lane);
+                    const bool take = ob > best || (ob == best && orow < brow);
+                    best = take ? ob : best;
+                    brow = take ? orow : brow;
+                    bval = take ? oval : bval;
+                }
+                {
+                    const float ob = xmove<32>(best, lane);
+                    const int orow = xmove<32>(brow, lane);
+                    const float oval = xmove<32>(bval, lane);
+                    const bool take = ob > best || (ob == best && orow < brow);
+                    brow = take ? orow : brow;
+                    bval = take ? oval : bval;
+                }
+                if (kk == 0) cand[wave * BN + 16 * ct + i16] = SignCand{bval, brow};
+            }
+        }
+        __syncthreads();
+        if (t < n) {
+            float best = -1.f, bval = 0.f;
+            int brow = 1 << 20;
+            for (int w = 0; w < BT / 64 && 16 * w < n; ++w) {
+                const SignCand cw = cand[w * BN + t];
+                const float av = f_abs(cw.val);
+                const bool take = cw.row < n && (av > best || (av == best && cw.row < brow));
+                best = take ? av : best;
+                brow = take ? cw.row : brow;
+                bval = take ? cw.val : bval;
+            }
+            csign[t] = (bval < 0.f) ? -1.f : 1.f;
+        }
+        __syncthreads();
+        if (rows) {
+#pragma unroll
+            for (int ct = 0; ct < BN / 16; ++ct) {
+                const int c = 16 * ct + i16;
+                const float sgn = (c < n) ? csign[c] : 1.f;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * wave + MF::crow(lane, v);
+                    if (row < n && c < n) Qb[row * n + c] = sgn * acc[ct][v];
+                }
             }
         }
     }
