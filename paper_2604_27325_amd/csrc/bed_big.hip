@@ -193,15 +193,17 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, Ws ws)
         // lane's columns that lie at or left of column k (v is zero there and
         // the columns are never read again), and whole waves whose rows are
         // all <= k (their p and w are not used).
-        // binary32 keeps v at its columns in registers (room under 128 VGPRs);
-        // binary64 forms it again in the update from the pivot pairs
-        constexpr bool HOLD = sizeof(H) == 4;
-        H vc[HOLD ? CPL : 1];
+        // v at this wave's columns c = g + 4j, the same for all its lanes: lane
+        // j forms column j's entry from one pivot pair and the values are
+        // broadcast into scalar registers (one LDS read per lane instead of
+        // one per column), where they stay for the update
+        const H2 xl = xe[g + 4 * (lane & (CPL - 1))];
+        const H vl = fma(xl.x, h.rv0, xl.y);
+        H vc[CPL];
         H pp = H(0);
         if (wlive(k)) {
-            // independent chains against the FMA latency: four in binary64,
-            // two in binary32 (whose 128-register budget has no room for more)
-            constexpr int NC = sizeof(H) / 2;
+            // independent chains against the FMA latency
+            constexpr int NC = 4;
             H pq[NC];
 #pragma unroll
             for (int i = 0; i < NC; ++i) pq[i] = H(0);
@@ -211,15 +213,11 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, Ws ws)
 #pragma unroll
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
-                    const H2 xc = xe[g + 4 * j];
-                    const H vj = fma(xc.x, h.rv0, xc.y);
-                    if constexpr (HOLD) vc[j] = vj;
-                    pq[jj % NC] = fma(ar[j], vj, pq[jj % NC]);
+                    vc[j] = bcast(vl, j);
+                    pq[jj % NC] = fma(ar[j], vc[j], pq[jj % NC]);
                 }
             }
-#pragma unroll
-            for (int i = 1; i < NC; ++i) pq[0] += pq[i];
-            pp = pq[0];
+            pp = (pq[0] + pq[1]) + (pq[2] + pq[3]);
             S.u.s.part[g][r] = pp;
         }
         const H pv = wave_sum_all(vr * pp);  // partial of v^T A v
@@ -246,14 +244,7 @@ k_big_reduce(const float *__restrict__ A, int n, int64_t batch, Ws ws)
                 for (int jj = 0; jj < 8; ++jj) {
                     const int j = 8 * q + jj;
                     const int c = g + 4 * j;
-                    H vj;
-                    if constexpr (HOLD) {
-                        vj = vc[j];
-                    } else {
-                        const H2 xc = xe[c];
-                        vj = fma(xc.x, h.rv0, xc.y);
-                    }
-                    ar[j] = fma(-vr, S.u.s.w[c], fma(-wr, vj, ar[j]));
+                    ar[j] = fma(-vr, S.u.s.w[c], fma(-wr, vc[j], ar[j]));
                 }
             }
         }
