@@ -15,7 +15,9 @@
 //                 Q_H = I) solves T1 and T2
 //   k_big_merge   z = [sgn(beta) Q1(s-1, :), Q2(0, :)] (Eq. (5)), deflation,
 //                 secular roots, Loewner vectors and the merge matrix M;
-//                 Q = (Q_H diag(Q1, Q2)) M on 16x16x4 MFMA tiles, sign rule
+//                 Q = Q_H (diag(Q1, Q2) M) on 16x16x4 MFMA tiles, sign rule
+// Every kernel fits two 512-thread teams per CU (at most 128 VGPRs and 80 KB
+// of LDS each).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,8 +44,9 @@ struct Meta {
     int pad;
 };
 
-// Workspace of one batch: children (dense input, eigenvectors, eigenvalues,
-// info) and per-matrix meta data.  For even n the two children's arrays are
+// Workspace of one batch: children (tridiagonal input, eigenvectors,
+// eigenvalues, info), per-matrix meta data and, with eigenvectors, the
+// reflectors.  For even n the two children's arrays are
 // contiguous (child 2 of matrix b follows all children 1), so one uniform
 // launch solves both.
 struct Ws {
