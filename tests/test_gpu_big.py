@@ -184,3 +184,17 @@ def test_graph_capture_eigenvalues_only():
         torch.cuda.synchronize()
         _ = (A * 2.0).sum().item()
         assert torch.equal(lam, ref), f"replay {rep}"
+
+
+def test_in_place_q_over_a():
+    """Q == A (in place) at n = 128: the reduction reads A before the
+    Householder product is written over it; the result equals the
+    out-of-place solve bitwise."""
+    rng = np.random.default_rng(8600)
+    A = torch.from_numpy(workloads.gaussian_sym(rng, 6, 128).astype(np.float32)).to(DEV)
+    lam_r, Q_r = bed.syevd(A)
+    B = A.clone()
+    lam = torch.empty(6 * 128, device=DEV)
+    bed.syevd_packed([128] * 6, B.view(-1), lam=lam, Q=B.view(-1))
+    torch.cuda.synchronize()
+    assert torch.equal(lam.view(6, 128), lam_r) and torch.equal(B, Q_r)
