@@ -11,8 +11,9 @@
 //                 eigenvectors the reflectors go to the workspace
 //   k_big_qh      Q_H = H_0 ... H_{n-3} from the reflectors in compact-WY
 //                 blocks on binary64 MFMA tiles, staged in the Q output
-//   children      the n <= 64 solver on tridiagonal input (no reduction,
-//                 Q_H = I) solves T1 and T2
+//   children      the n <= 64 solver on tridiagonal input (no reduction, no
+//                 back-transform) solves T1 and T2; for eigenvalues alone it
+//                 returns only the end rows of their eigenvector matrices
 //   k_big_merge   z = [sgn(beta) Q1(s-1, :), Q2(0, :)] (Eq. (5)), deflation,
 //                 secular roots, Loewner vectors and the merge matrix M;
 //                 Q = Q_H (diag(Q1, Q2) M) on 16x16x4 MFMA tiles, sign rule
@@ -57,6 +58,8 @@ struct Ws {
     Meta *meta;
     float *v;    // with eigenvectors: reflectors v_0 .. v_{n-3} (binary32 rows of n)
     float *tau;  // their tau (zero for a skipped step), n per matrix
+    float *e1, *e2;  // eigenvalues only: the children's first and last eigenvector
+                     // rows (2 n1 and 2 n2 values apart), in the q1 space
 };
 
 // ------------------------------------------------------------------ reduction
@@ -495,7 +498,10 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
     float *lamc = S.M, *zin = S.M + LD;
     if (t < n) {
         lamc[t] = (t < n1) ? ws.l1[bi * n1 + t] : ws.l2[bi * n2 + t - n1];
-        zin[t] = (t < n1) ? sgm * Q1[(n1 - 1) * n1 + t] : Q2[t - n1];
+        if (Qb)
+            zin[t] = (t < n1) ? sgm * Q1[(n1 - 1) * n1 + t] : Q2[t - n1];
+        else  // the children's end rows (last row of Q1 second, first row of Q2 first)
+            zin[t] = (t < n1) ? sgm * ws.e1[bi * 2 * n1 + n1 + t] : ws.e2[bi * 2 * n2 + t - n1];
     }
     if (t == 0) {
         S.capped = 0;
@@ -901,6 +907,8 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
     ws.v = Q ? (float *)(base + c_bytes + q_bytes + l_bytes + i_bytes + m_bytes) : nullptr;
     ws.tau = Q ? (float *)(base + c_bytes + q_bytes + l_bytes + i_bytes + m_bytes + v_bytes)
                : nullptr;
+    ws.e1 = Q ? nullptr : ws.q1;
+    ws.e2 = Q ? nullptr : ws.q1 + B * 2 * n1;
 
     if (Q)
         hipLaunchKernelGGL(k_big_reduce<double>, dim3((unsigned)batch), dim3(BT), 0, s,
@@ -917,14 +925,17 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
         if (e != hipSuccess) return hip_fail(e, "k_big_qh launch");
     }
     const bed_tune dflt = default_tune();
+    // the halves: eigenvectors, or (eigenvalues only) just the end rows z needs
+    float *q1 = Q ? ws.q1 : nullptr, *q2 = Q ? ws.q2 : nullptr;
     if (n1 == n2) {
-        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1, ws.q1,
-                       ws.i1, s);
+        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, 2 * batch, ws.l1, q1,
+                       ws.i1, ws.e1, s);
     } else {
-        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, batch, ws.l1, ws.q1, ws.i1, s);
+        e = launch_tri(class_shape(size_class(n1), dflt), ws.c1, n1, batch, ws.l1, q1, ws.i1,
+                       ws.e1, s);
         if (e == hipSuccess)
-            e = launch_tri(class_shape(size_class(n2), dflt), ws.c2, n2, batch, ws.l2, ws.q2,
-                           ws.i2, s);
+            e = launch_tri(class_shape(size_class(n2), dflt), ws.c2, n2, batch, ws.l2, q2,
+                           ws.i2, ws.e2, s);
     }
     if (e != hipSuccess) return hip_fail(e, "child solve launch");
     hipLaunchKernelGGL(k_big_merge, dim3((unsigned)batch), dim3(BT), 0, s, n, (int64_t)batch,

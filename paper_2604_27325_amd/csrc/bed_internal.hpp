@@ -51,9 +51,11 @@ hipError_t launch_uniform(bed_dtype dt, TeamShape ts, const void *A, int n, int6
                           void *lam, void *Q, int32_t *info, hipStream_t s);
 
 // Uniform batch of binary32 tridiagonal matrices (diagonal then off-diagonal,
-// 2n values apart) with eigenvectors; team shapes (32, 128) and (64, 512).
+// 2n values apart); team shapes (32, 128) and (64, 512).  With Q == nullptr
+// (eigenvalues only) ends, if not null, receives each matrix's first and last
+// eigenvector rows (2n values apart).
 hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, float *lam, float *Q,
-                      int32_t *info, hipStream_t s);
+                      int32_t *info, float *ends, hipStream_t s);
 
 // Work-list launch.  counter == nullptr: workgroup i handles items i, i+grid,
 // ... (static).  counter != nullptr: persistent workgroups pull items from

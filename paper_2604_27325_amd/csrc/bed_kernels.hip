@@ -27,18 +27,21 @@ k_syevd_uniform(const T *__restrict__ A, int n, int64_t batch, T *__restrict__ l
 }
 
 // Uniform batch of tridiagonal matrices: matrix b is the diagonal (n values)
-// then the off-diagonal (n - 1 values) at tri + 2 n b.
+// then the off-diagonal (n - 1 values) at tri + 2 n b.  Without Q, ends
+// (nullable) receives the first and last rows of each eigenvector matrix at
+// ends + 2 n b.
 template <typename T, int NMAX, int NT>
 __global__ void __launch_bounds__(NT) BED_OCC(NMAX, NT)
 k_syevd_tri(const T *__restrict__ tri, int n, int64_t batch, T *__restrict__ lam,
-            T *__restrict__ Q, int32_t *__restrict__ info, int leaf)
+            T *__restrict__ Q, int32_t *__restrict__ info, T *__restrict__ ends, int leaf)
 {
     __shared__ Smem<T, NMAX, NT> S;
     const int64_t b = blockIdx.x;
     if (b >= batch) return;
     const int64_t n2 = (int64_t)n * n;
     syevd_team<T, NMAX, NT, true>(tri + b * 2 * n, n, lam + b * n, Q ? Q + b * n2 : nullptr,
-                                  info ? info + b : nullptr, S, threadIdx.x, leaf);
+                                  info ? info + b : nullptr, S, threadIdx.x, leaf,
+                                  ends ? ends + b * 2 * n : nullptr);
 }
 
 // Static schedule: workgroup b solves item b.  The hardware dispatcher
@@ -132,14 +135,14 @@ static hipError_t uniform_t(TeamShape ts, const void *A, int n, int64_t batch, v
 }
 
 hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, float *lam, float *Q,
-                      int32_t *info, hipStream_t s)
+                      int32_t *info, float *ends, hipStream_t s)
 {
     if (batch <= 0) return hipSuccess;
     if (!leaf_supported(ts.leaf)) return hipErrorInvalidValue;
 #define X(NM, NTT)                                                                          \
     if (ts.nmax == NM && ts.nt == NTT) {                                                    \
         hipLaunchKernelGGL((k_syevd_tri<float, NM, NTT>), dim3((unsigned)batch), dim3(NTT), \
-                           0, s, tri, n, batch, lam, Q, info, ts.leaf);                     \
+                           0, s, tri, n, batch, lam, Q, info, ends, ts.leaf);               \
         return hipGetLastError();                                                           \
     }
     X(32, 128)

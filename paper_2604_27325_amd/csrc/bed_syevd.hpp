@@ -1093,12 +1093,15 @@ __device__ __forceinline__ int householder(Smem<T, NMAX, NT>& S, const int n, co
 
 // TRI: the input is already tridiagonal, given as its diagonal a (n values)
 // followed by its off-diagonal b (n - 1 values) at Ain; there is no reduction
-// and Q_H is the identity.
+// and Q_H is the identity, so Q is Q_T (no back-transform).  ends_out (TRI,
+// eigenvalues only): the first and last rows of Q_T, all that a merge above
+// reads (Eq. (5)), as 2n values.
 template <typename T, int NMAX, int NT, bool TRI = false>
 __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int n,
                                            T* __restrict__ lam_out, T* __restrict__ Q_out,
                                            int* __restrict__ info_out, Smem<T, NMAX, NT>& S,
-                                           const int t, const int leaf = 4)
+                                           const int t, const int leaf = 4,
+                                           T* __restrict__ ends_out = nullptr)
 {
     static_assert(NMAX <= 64 && (NMAX & (NMAX - 1)) == 0, "NMAX: power of two <= 64");
     static_assert(NT % 64 == 0 && NT >= NMAX && NT % NMAX == 0, "team geometry");
@@ -1226,7 +1229,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     // back-multiplication reads them against zero A entries.
     for (int e = t; e < NMAX * LD; e += NT) S.M[e] = T(0);
     team_sync<NT>();
-    if constexpr (AW > 0) {
+    if constexpr (AW > 0 && !TRI) {
         // every reflector has been read: Q_H replaces them
         if (qh_wave) {
             constexpr int RW = QhShape<T, NMAX, NT>::RW;
@@ -1554,11 +1557,18 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
     if (!Q_out) {  // eigenvalues only
         for (int e = t; e < n; e += NT) lam_out[e] = fexp<T>::pow2(-input_shift(S)) * Lc[e];
         if (t == 0 && info_out) *info_out = S.capped;
+        if constexpr (TRI) {
+            // the root's end rows, carried through every depth
+            if (ends_out)
+                for (int e = t; e < 2 * n; e += NT)
+                    ends_out[e] = (e < n) ? Qc[e] : Qc[(n - 1) * LD + e - n];
+        }
         return;
     }
 
     // ------------------------------------------------------------ back-transform
-    if constexpr (AW > 0) {
+    // (TRI: Q_H = I, the compact-WY branch with no reflectors stores Q_T)
+    if constexpr (AW > 0 && !TRI) {
         // Q_A = Q_H Q_T on 16x16x4 MFMA tiles: wave w computes row tiles
         // [p RPW, p RPW + RPW) of column tile w % CT (p = w / CT).  Lane group kk
         // covers k in [kk KS, kk KS + KS), so each lane reads a contiguous
@@ -1687,7 +1697,7 @@ __device__ __forceinline__ void syevd_team(const T* __restrict__ Ain, const int 
         using MF = Mf<T>;
         constexpr int RT = NMAX / 16;
         constexpr int VLD = Smem<T, NMAX, NT>::VLD;
-        const int nb = n > 2 ? n - 2 : 0;  // reflectors
+        const int nb = (!TRI && n > 2) ? n - 2 : 0;  // reflectors
         const int NB = (nb + 15) / 16;
         const int i16 = lane & 15;
         BED_MARK(7, 0);
