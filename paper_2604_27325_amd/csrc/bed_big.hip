@@ -474,7 +474,6 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
             int32_t *__restrict__ info, Ws ws)
 {
     __shared__ MrgSmem S;
-    using MF = Mf<float>;
     constexpr int LD = MrgSmem::LD;
     const int64_t bi = blockIdx.x;
     if (bi >= batch) return;
