@@ -141,7 +141,7 @@ def test_wilkinson_w21():
 
 
 # ---------------------------------------------------------------- brute force
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 11, 16, 24, 33, 48, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 11, 16, 24, 33, 48, 64, 65, 97, 128])
 def test_vs_cyclic_jacobi(n):
     rng = np.random.default_rng(100 + n)
     for kind in ("gauss", "cov"):
