@@ -198,3 +198,14 @@ def test_in_place_q_over_a():
     bed.syevd_packed([128] * 6, B.view(-1), lam=lam, Q=B.view(-1))
     torch.cuda.synchronize()
     assert torch.equal(lam.view(6, 128), lam_r) and torch.equal(B, Q_r)
+
+
+def test_every_order_65_to_128():
+    """Every order above 64, two matrices each (one Gaussian, one covariance),
+    eigenvectors and eigenvalues only: all tearing splits n1 = n2 and
+    n2 = n1 + 1 with children of 32 .. 64."""
+    for n in range(65, 129):
+        rng = np.random.default_rng(8700 + n)
+        A = np.concatenate([workloads.gaussian_sym(rng, 1, n), workloads.covariance(rng, 1, n)])
+        check(A.astype(np.float32), f"n={n}")
+        check(A.astype(np.float32), f"eigenvalues n={n}", vectors=False)
