@@ -5,7 +5,7 @@ include/bed_probe.h) on the batch-512 workload and prints, as markdown, the
 mean time of every phase over the teams and the cycle breakdown of one
 Householder step.
 
-    python -m paper_2604_27325_amd.probe --n 64 [--threads 512]
+    python -m paper_2604_27325_amd.probe --n 64 [--threads 512] [--batch 256]
 """
 import argparse
 import ctypes
@@ -37,7 +37,7 @@ def phase_names(n):
     return out
 
 
-def run(n, threads, dtype="f32", lib_path=PROBE_LIB):
+def run(n, threads, dtype="f32", lib_path=PROBE_LIB, batch=512):
     import torch
 
     from paper_2604_27325_amd import load_library, workloads
@@ -47,6 +47,7 @@ def run(n, threads, dtype="f32", lib_path=PROBE_LIB):
     lib.bed_probe_phases.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int64, vp, vp, vp, vp, vp, vp, vp]
     A_np, _, _ = workloads.paper_scale(n)
+    A_np = A_np[:batch]
     dt = torch.float32 if dtype == "f32" else torch.float64
     A = torch.from_numpy(A_np).to("cuda", dt)
     b = A.shape[0]
@@ -69,7 +70,7 @@ def run(n, threads, dtype="f32", lib_path=PROBE_LIB):
 
 def report(n, threads, hstep, marks, steps, defl=None):
     order = phase_names(n)
-    lines = [f"phase timing, batch 512 n={n} FP32, {threads} threads per matrix "
+    lines = [f"phase timing, batch {marks.shape[0]} n={n} FP32, {threads} threads per matrix "
              "(mean over teams, 100 MHz clock)", "", "| phase | mean us | max us |", "|---|---|---|"]
     prev = marks[:, 0]
     total = np.zeros(marks.shape[0])
@@ -110,10 +111,12 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--lib", default=PROBE_LIB, help="probe library to load")
+    ap.add_argument("--batch", type=int, default=512,
+                    help="matrices (at most 512; 256 puts one team on each CU)")
     a = ap.parse_args()
     threads = a.threads or (64 if a.n <= 16 else (128 if a.n <= 32 else 512))
     hstep = 8 if a.n <= 16 else (16 if a.n <= 32 else 32)
-    marks, steps, defl = run(a.n, threads, lib_path=a.lib)
+    marks, steps, defl = run(a.n, threads, lib_path=a.lib, batch=a.batch)
     print(report(a.n, threads, hstep, marks, steps, defl))
 
 
