@@ -104,7 +104,10 @@ typedef struct bed_plan bed_plan;
  * kernels, the top merge) with a workspace kept per stream (about
  * 8 (n/2)^2 + 12n + 24 bytes per matrix, plus 4n(n - 1) with eigenvectors,
  * grown on demand; growing it synchronizes the stream and is refused under
- * capture). */
+ * capture).  A workspace that a HIP graph captured is kept until the process
+ * ends (a larger one replaces it for later calls); the graph's replays share
+ * it with later calls on the capture stream that fit in it, so replay the
+ * graph on that stream or keep the two from overlapping. */
 bed_status bed_syevd(bed_dtype dt, int64_t batch, const int32_t *n, const void *A, void *lambda,
                      void *Q, int32_t *info, void *stream);
 

@@ -829,14 +829,18 @@ k_big_merge(int n, int64_t batch, float *__restrict__ lam, float *__restrict__ Q
 }
 
 // ------------------------------------------------------------------ host
-// One workspace per stream (grown on demand; a buffer in use by a captured
-// graph is pinned and never freed).
+// One workspace per stream, grown on demand.  A buffer that a captured graph
+// uses is pinned: it is never freed, and a stream whose pinned buffer is too
+// small for a later call gets a new one while the old one stays, retired,
+// until the process ends.
 struct Buf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool pinned = false;
 };
 std::mutex g_mu;
 Lru<void *, Buf> g_bufs(8);
+std::vector<void *> g_retired;
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -869,12 +873,17 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
             if (capturing)
                 return fail(BED_ERR_CAPTURE, "workspace for n > 64 would be allocated during capture");
             if (b) {
-                hipError_t e = hipStreamSynchronize(s);
-                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-                (void)hipFree(b->ptr);
+                if (b->pinned) {
+                    g_retired.push_back(b->ptr);  // a graph still reads and writes it
+                } else {
+                    hipError_t e = hipStreamSynchronize(s);
+                    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+                    (void)hipFree(b->ptr);
+                }
                 b->ptr = nullptr;
                 b->bytes = 0;
-                e = hipMalloc(&b->ptr, need);
+                b->pinned = false;
+                hipError_t e = hipMalloc(&b->ptr, need);
                 if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
                 b->bytes = need;
             } else {
@@ -890,7 +899,10 @@ bed_status big_solve(bed_dtype dt, int64_t batch, int n, const void *A, void *la
                 b = g_bufs.find((void *)s);
             }
         }
-        if (capturing) g_bufs.pin((void *)s);
+        if (capturing) {
+            g_bufs.pin((void *)s);
+            b->pinned = true;
+        }
         base = (char *)b->ptr;
     }
     Ws ws;

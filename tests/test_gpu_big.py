@@ -186,6 +186,41 @@ def test_graph_capture_eigenvalues_only():
         assert torch.equal(lam, ref), f"replay {rep}"
 
 
+def test_graph_keeps_workspace_when_stream_grows():
+    """A graph captured at n = 100 keeps its workspace after a larger eager
+    call (n = 128, more matrices) on the capture stream has grown that
+    stream's workspace: replays after the growth still equal the eager
+    result bitwise, and so does the larger call."""
+    rng = np.random.default_rng(8502)
+    A = torch.from_numpy(workloads.gaussian_sym(rng, 16, 100).astype(np.float32)).to(DEV)
+    A2 = torch.from_numpy(workloads.gaussian_sym(rng, 48, 128).astype(np.float32)).to(DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ref_l, ref_q = bed.syevd(A, stream=s)
+    torch.cuda.synchronize()
+    lam = torch.empty_like(ref_l)
+    Q = torch.empty_like(ref_q)
+    info = torch.empty(16, dtype=torch.int32, device=DEV)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        bed.syevd_packed([100] * 16, A.view(-1), lam=lam.view(-1), Q=Q.view(-1), info=info,
+                         stream=s)
+    ref2_l, ref2_q = bed.syevd(A2)  # default stream: its own workspace
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        l2, q2 = bed.syevd(A2, stream=s)  # grows the capture stream's workspace
+    torch.cuda.synchronize()
+    assert torch.equal(l2, ref2_l) and torch.equal(q2, ref2_q)
+    for rep in range(2):
+        lam.fill_(-1.0)
+        Q.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(lam, ref_l) and torch.equal(Q, ref_q), f"replay {rep}"
+
+
 def test_in_place_q_over_a():
     """Q == A (in place) at n = 128: the reduction reads A before the
     Householder product is written over it; the result equals the
