@@ -175,7 +175,9 @@ bed_status bed_tune_set(bed_dtype dt, int64_t batch, const int32_t *n, const bed
  * plan per (dtype, size mix, stream), at most 32 (least recently used evicted
  * once its last launch has completed), except that plans used under stream
  * capture are kept for the life of the process (a graph holds their device
- * pointers). */
+ * pointers).  Such a graph's replays share the plan, and a persistent plan's
+ * work counter, with later calls of the same size mix on the capture stream:
+ * replay the graph on that stream or keep the two from overlapping. */
 int32_t bed_cache_entries(void);
 
 /* Backward of A = Q diag(lambda) Q^T (for differentiable use, Sec. 1):
