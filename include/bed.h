@@ -74,7 +74,7 @@ typedef enum {
  *                 form while four form the Householder product, which 256 and
  *                 fewer apply in compact-WY form instead)
  *   threads_mid   threads per matrix for 16 < n <= 32 (64, 128 or 256; default
- *                 128; 256 reduces on two waves while two form Q_H)
+ *                 256: one wave reduces, two form Q_H, all four merge)
  *   waves_per_cu  resident teams per compute unit for the persistent launch
  *   order         0: largest n first (LPT), 1: input order
  *   persistent    1: one persistent launch pulls matrices from a device work

@@ -100,7 +100,7 @@ bed_tune default_tune()
 {
     bed_tune t;
     t.threads_big = 512;
-    t.threads_mid = 128;
+    t.threads_mid = 256;
     t.waves_per_cu = 0;
     t.order = 0;
     t.persistent = 0;

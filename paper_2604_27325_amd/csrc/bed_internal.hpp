@@ -51,7 +51,7 @@ hipError_t launch_uniform(bed_dtype dt, TeamShape ts, const void *A, int n, int6
                           void *lam, void *Q, int32_t *info, hipStream_t s);
 
 // Uniform batch of binary32 tridiagonal matrices (diagonal then off-diagonal,
-// 2n values apart); team shapes (32, 128) and (64, 512).  With Q == nullptr
+// 2n values apart); team shapes (32, 128), (32, 256) and (64, 512).  With Q == nullptr
 // (eigenvalues only) ends, if not null, receives each matrix's first and last
 // eigenvector rows (2n values apart).
 hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, float *lam, float *Q,

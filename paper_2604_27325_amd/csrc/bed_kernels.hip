@@ -146,6 +146,7 @@ hipError_t launch_tri(TeamShape ts, const float *tri, int n, int64_t batch, floa
         return hipGetLastError();                                                           \
     }
     X(32, 128)
+    X(32, 256)
     X(64, 512)
 #undef X
     return hipErrorInvalidValue;

@@ -54,11 +54,10 @@ namespace bed {
 
 // Waves that run the Householder reduction of a team: the row block of a
 // wave (NMAX^2/(64 HW) registers per lane) must fit the register budget.
-// n <= 32 takes two reducing waves in a team of four or more (the other two
-// form Q_H), one otherwise.
+// n <= 32 reduces on one wave at every team size (a second one costs its
+// cross-wave exchange in every step; larger teams still widen the merges).
 #ifndef BED_HH_WAVES
-#define BED_HH_WAVES(T, NMAX, NT) \
-    ((NMAX) == 64 ? ((NT) / 64 < 4 ? (NT) / 64 : 4) : (((NMAX) == 32 && (NT) >= 256) ? 2 : 1))
+#define BED_HH_WAVES(T, NMAX, NT) ((NMAX) == 64 ? ((NT) / 64 < 4 ? (NT) / 64 : 4) : 1)
 #endif
 template <typename T, int NMAX, int NT> struct HH_WAVES {
     static constexpr int value = BED_HH_WAVES(T, NMAX, NT);

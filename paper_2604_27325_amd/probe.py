@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--batch", type=int, default=512,
                     help="matrices (at most 512; 256 puts one team on each CU)")
     a = ap.parse_args()
-    threads = a.threads or (64 if a.n <= 16 else (128 if a.n <= 32 else 512))
+    threads = a.threads or (64 if a.n <= 16 else (256 if a.n <= 32 else 512))
     hstep = 8 if a.n <= 16 else (16 if a.n <= 32 else 32)
     marks, steps, defl = run(a.n, threads, lib_path=a.lib, batch=a.batch)
     print(report(a.n, threads, hstep, marks, steps, defl))
