@@ -40,7 +40,7 @@ def nmax_of(n):
 
 def threads_of(n):
     """Threads per matrix of the default schedule for order n."""
-    return {16: 64, 32: 128, 64: 512}[nmax_of(n)]
+    return {16: 64, 32: 256, 64: 512}[nmax_of(n)]
 
 
 def merge_tree(n):
