@@ -46,7 +46,7 @@ def test_paper_scale_fp32_batch512(n):
     check(A, f"paper scale n={n}")
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 9, 15, 16, 17, 23, 31, 33, 40, 47, 63, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 9, 15, 16, 17, 23, 24, 31, 32, 33, 40, 47, 63, 64])
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
 def test_every_size_class_and_ragged_tail(n, dt):
     rng = np.random.default_rng(500 + n)
